@@ -1,0 +1,110 @@
+"""The oracle's pins must be sensitive: plant plausible mistakes in a copy of
+the oracle source (on the CPU, in a temporary directory), build each mutant
+and check that the pin checks below reject every one of them while the
+unmodified source passes."""
+import ctypes
+import math
+import os
+import random
+import subprocess
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_1505_05571_amd import workloads as W
+
+SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                   "oracle", "exsum_oracle.c")
+
+MUTANTS = {
+    "implicit_bit_dropped": ("M = e ? (m | (1ull << 52)) : m;", "M = m;"),
+    "denormal_exponent": ("uint64_t e_eff = e ? e : 1;", "uint64_t e_eff = e ? e : 2;"),
+    "ties_away": ("up = round_bit && (sticky || (q & 1));", "up = round_bit;"),
+    "sign_swapped": ("wide_add_shifted(s ? &acc->neg : &acc->pos, M, (int)(e_eff - 1));\n}\n\n/* Same",
+                     "wide_add_shifted(s ? &acc->pos : &acc->neg, M, (int)(e_eff - 1));\n}\n\n/* Same"),
+    "exponent_off_by_one": ("uint64_t E = (uint64_t)sh + 1;", "uint64_t E = (uint64_t)sh + 2;"),
+    "carry_dropped": ("uint64_t carry = a->w[limb] < old;", "uint64_t carry = 0;"),
+    "overflow_threshold": ("if (E >= emax) return emax << mbits;", "if (E > emax) return emax << mbits;"),
+    "sticky_ignored": ("int sticky = wide_any_below(&Q, sh - 1) || R != 0;", "int sticky = R != 0;"),
+    "shift_off_by_one": ("(int)(e_eff - 1));\n}\n\n/* Same", "(int)(e_eff));\n}\n\n/* Same"),
+}
+
+
+def bits(v) -> int:
+    return int(np.array([v], dtype=np.float64).view(np.uint64)[0])
+
+
+def exact_round(values) -> int:
+    s = sum((Fraction(float(v)) for v in values), Fraction(0))
+    if s == 0:
+        return 0
+    try:
+        return bits(float(s))
+    except OverflowError:
+        return bits(math.inf if s > 0 else -math.inf)
+
+
+def build_variant(tmp_path, name, text):
+    c = tmp_path / (name + ".c")
+    so = tmp_path / (name + ".so")
+    c.write_text(text)
+    subprocess.run(["gcc", "-O1", "-fPIC", "-shared", "-pthread", "-ffp-contract=off",
+                    "-o", str(so), str(c)], check=True)
+    lib = ctypes.CDLL(str(so))
+    lib.exo_sum_f64.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+    lib.exo_sum_f64.restype = ctypes.c_uint64
+    return lib
+
+
+def pins_pass(lib) -> bool:
+    def s(vals):
+        a = np.ascontiguousarray(vals, dtype=np.float64)
+        return int(lib.exo_sum_f64(ctypes.c_void_p(a.ctypes.data), a.size))
+
+    rng = random.Random(2)
+    checks = []
+    # worked example
+    checks.append(s([1e15, -1e15, 0.1]) == bits(0.1))
+    # one and two terms against hardware
+    rb = W.random_bits(2000, seed=1)
+    checks.append(all(s([v]) == bits(v) for v in rb[:500] if v != 0))
+    checks.append(all(s([rb[i], rb[i + 1]]) == bits(rb[i] + rb[i + 1])
+                      for i in range(0, 2000, 2) if math.isfinite(rb[i] + rb[i + 1])
+                      and rb[i] + rb[i + 1] != 0))
+    d = np.array([3e-320, -5e-321, 2.2e-308, 1.0, -(2.0 ** -1022)])
+    checks.append(s(d) == exact_round(d))
+    # overflow closed forms
+    dmax = np.finfo(np.float64).max
+    checks.append(s([dmax, 2.0 ** 970]) == bits(math.inf))
+    checks.append(s([dmax, 2.0 ** 970, -5e-324]) == bits(dmax))
+    checks.append(s([dmax, 2.0 ** 1023]) == bits(math.inf))
+    checks.append(s([-dmax, -dmax, -dmax]) == bits(-math.inf))
+    # exact ties and near ties (round half to even)
+    for _ in range(200):
+        e = rng.randint(-1000, 1000)
+        xv = math.ldexp(rng.getrandbits(52) | (1 << 52), e - 52)
+        half = math.ldexp(1.0, e - 53)
+        for tiny in (half, -half, half * (1 + 2 ** -40)):
+            checks.append(s([xv, tiny]) == exact_round([xv, tiny]))
+    # brute force
+    for _ in range(300):
+        vals = [math.ldexp(rng.uniform(-1, 1), rng.randint(-1074, 1023)) for _ in range(rng.randint(1, 6))]
+        checks.append(s(vals) == exact_round(vals))
+    x = W.uniform_exponent(3000, seed=4)
+    checks.append(s(x) == bits(math.fsum(x)))
+    return all(checks)
+
+
+def test_unmodified_oracle_passes(tmp_path):
+    text = open(SRC).read()
+    assert pins_pass(build_variant(tmp_path, "orig", text))
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(tmp_path, name):
+    old, new = MUTANTS[name]
+    text = open(SRC).read()
+    assert old in text, "mutation site not found: " + name
+    mutated = text.replace(old, new, 1)
+    assert pins_pass(build_variant(tmp_path, name, mutated)) is False
