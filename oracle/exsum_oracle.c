@@ -129,12 +129,6 @@ static void wide_sub(wide_t *r, const wide_t *a, const wide_t *b)
     }
 }
 
-static int wide_is_zero(const wide_t *a)
-{
-    for (int i = 0; i < LIMBS; i++) if (a->w[i]) return 0;
-    return 1;
-}
-
 /* number of significant bits (0 for zero) */
 static int wide_bitlen(const wide_t *a)
 {

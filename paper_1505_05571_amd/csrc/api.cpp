@@ -1,0 +1,250 @@
+// api.cpp -- the C ABI of include/exsum.h: argument checks, per-stream
+// workspaces, launch planning.  No arithmetic on terms happens here; every
+// step of the sum runs in the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "exsum.h"
+#include "exsum_internal.h"
+
+namespace exsum {
+namespace {
+
+std::mutex g_mu;
+std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+
+exsum_config default_config() {
+  exsum_config c;
+  c.large_block = 256;
+  c.large_vec = 4;
+  c.large_grid = 0;
+  c.precombine = 16;
+  c.small_max = 4096;
+  c.small_grid = 0;
+  c.seg_grid = 0;
+  c.seg_small_max = 2048;
+  c.seg_tile = 65536;
+  return c;
+}
+
+exsum_config g_cfg = default_config();
+int g_cu[64] = {0};
+
+constexpr int64_t kMaxN = int64_t(1) << 40;
+constexpr int kMaxGrid = 8192;
+
+bool valid_large(int block, int vec) {
+  return (block == 256 && (vec == 2 || vec == 4 || vec == 6)) || (block == 512 && (vec == 2 || vec == 3));
+}
+
+bool config_ok(const exsum_config &c) {
+  if (!valid_large(c.large_block, c.large_vec)) return false;
+  if (c.large_grid < 0 || c.large_grid > kMaxGrid) return false;
+  if (c.precombine < 0 || c.precombine > 64) return false;
+  if (c.small_max < 0 || c.small_grid < 0 || c.small_grid > kMaxGrid) return false;
+  if (c.seg_grid < 0 || c.seg_grid > kMaxGrid) return false;
+  if (c.seg_small_max < 0 || c.seg_small_max > 65536) return false;
+  if (c.seg_tile < 4096 || c.seg_tile % 4096 != 0 || c.seg_tile > (int64_t(1) << 30)) return false;
+  return true;
+}
+
+int status_of(hipError_t e) {
+  if (e == hipSuccess) return EXSUM_OK;
+  (void)hipGetLastError();
+  return e == hipErrorOutOfMemory ? EXSUM_ENOMEM : EXSUM_EDEVICE;
+}
+
+int cu_count(int dev) {
+  if (dev < 0 || dev >= 64) return 256;
+  if (g_cu[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) {
+      (void)hipGetLastError();
+      v = 256;
+    }
+    g_cu[dev] = v;
+  }
+  return g_cu[dev];
+}
+
+// Workspace for (current device, stream); allocated and zeroed on first use.
+int get_workspace(hipStream_t s, Workspace **out, int *dev_out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return status_of(e);
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto key = std::make_pair(dev, s);
+  auto it = g_ws.find(key);
+  if (it == g_ws.end()) {
+    Workspace w;
+    w.max_grid = kMaxGrid;
+    void *p = nullptr;
+    const size_t bytes = kGlobalAccBytes + sizeof(double) * kMaxGrid + 256;
+    e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) return status_of(e);
+    e = hipMemset(p, 0, bytes);
+    if (e != hipSuccess) { (void)hipFree(p); return status_of(e); }
+    w.acc = reinterpret_cast<GlobalAcc *>(p);
+    w.partials = reinterpret_cast<double *>(static_cast<char *>(p) + kGlobalAccBytes);
+    w.ticket = reinterpret_cast<unsigned int *>(static_cast<char *>(p) + kGlobalAccBytes + sizeof(double) * kMaxGrid);
+    it = g_ws.emplace(key, w).first;
+  }
+  *out = &it->second;
+  if (dev_out) *dev_out = dev;
+  return EXSUM_OK;
+}
+
+int run_sum(const double *x, int64_t n, double *out, hipStream_t s, const exsum_config &c) {
+  if (n < 0 || n >= kMaxN || out == nullptr || (n > 0 && x == nullptr)) return EXSUM_EINVAL;
+  if (!config_ok(c)) return EXSUM_EINVAL;
+  Workspace *w = nullptr;
+  int dev = 0;
+  int st = get_workspace(s, &w, &dev);
+  if (st != EXSUM_OK) return st;
+  hipError_t e;
+  if (n <= c.small_max) {
+    int grid = c.small_grid;
+    if (grid == 0) grid = (int)std::min<int64_t>(std::max<int64_t>((n + 8191) / 8192, 1), 64);
+    e = launch_small(x, n, w->acc, out, s, grid);
+  } else {
+    int grid = c.large_grid;
+    if (grid == 0) {
+      const int64_t tile_terms = int64_t(2) * c.large_block * c.large_vec;
+      const int64_t want = (n + 4 * tile_terms - 1) / (4 * tile_terms);
+      grid = (int)std::min<int64_t>(std::max<int64_t>(want, 1), int64_t(3) * cu_count(dev));
+    }
+    e = launch_large(x, n, w->acc, out, s, c.large_block, c.large_vec, grid, c.precombine);
+  }
+  return status_of(e);
+}
+
+}  // namespace
+}  // namespace exsum
+
+using namespace exsum;
+
+extern "C" {
+
+const char *exsum_status_string(int status) {
+  switch (status) {
+    case EXSUM_OK: return "ok";
+    case EXSUM_EINVAL: return "invalid argument";
+    case EXSUM_ENOMEM: return "out of device memory";
+    case EXSUM_EDEVICE: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+int exsum_f64(const double *x, int64_t n, double *out, void *stream) {
+  exsum_config c;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    c = g_cfg;
+  }
+  return run_sum(x, n, out, static_cast<hipStream_t>(stream), c);
+}
+
+int exsum_f64_cfg(const double *x, int64_t n, double *out, void *stream, const exsum_config *cfg) {
+  if (cfg == nullptr) return EXSUM_EINVAL;
+  return run_sum(x, n, out, static_cast<hipStream_t>(stream), *cfg);
+}
+
+int exsum_inexact_f64(const double *x, int64_t n, double *out, void *stream) {
+  if (n < 0 || n >= kMaxN || out == nullptr || (n > 0 && x == nullptr)) return EXSUM_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace *w = nullptr;
+  int dev = 0;
+  int st = get_workspace(s, &w, &dev);
+  if (st != EXSUM_OK) return st;
+  const int64_t want = (n + 8191) / 8192;
+  const int grid = (int)std::min<int64_t>(std::max<int64_t>(want, 1),
+                                          std::min<int64_t>(int64_t(4) * cu_count(dev), w->max_grid));
+  return status_of(launch_inexact(x, n, w->partials, w->ticket, out, s, grid));
+}
+
+int exsum_segmented_f64(const double *x, const int64_t *offsets, int64_t nseg, double *out, void *stream) {
+  if (nseg < 0 || nseg >= (int64_t(1) << 31)) return EXSUM_EINVAL;
+  if (nseg == 0) return EXSUM_OK;
+  if (x == nullptr || offsets == nullptr || out == nullptr) return EXSUM_EINVAL;
+  exsum_config c;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    c = g_cfg;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace *w = nullptr;
+  int dev = 0;
+  int st = get_workspace(s, &w, &dev);
+  if (st != EXSUM_OK) return st;
+  int grid = c.seg_grid;
+  if (grid == 0) grid = 3 * cu_count(dev);
+  int64_t cap = 0;
+  void *ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (w->seg_cap < nseg) {
+      if (w->seg) {
+        // the previous workspace may still be in use by work on this stream
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return status_of(e);
+        (void)hipFree(w->seg);
+        w->seg = nullptr;
+        w->seg_bytes = 0;
+        w->seg_cap = 0;
+      }
+      const int64_t new_cap = std::max<int64_t>(nseg, 1024);
+      const size_t bytes = seg_workspace_bytes(new_cap);
+      void *p = nullptr;
+      hipError_t e = hipMalloc(&p, bytes);
+      if (e != hipSuccess) return status_of(e);
+      e = hipMemset(p, 0, bytes);
+      if (e != hipSuccess) { (void)hipFree(p); return status_of(e); }
+      w->seg = p;
+      w->seg_bytes = bytes;
+      w->seg_cap = new_cap;
+    }
+    cap = w->seg_cap;
+    ws = w->seg;
+  }
+  return status_of(launch_segmented(x, offsets, nseg, out, ws, cap, s, grid, c.seg_small_max, c.seg_tile,
+                                    c.precombine));
+}
+
+int exsum_get_config(exsum_config *cfg) {
+  if (cfg == nullptr) return EXSUM_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  *cfg = g_cfg;
+  return EXSUM_OK;
+}
+
+int exsum_set_config(const exsum_config *cfg) {
+  if (cfg == nullptr || !config_ok(*cfg)) return EXSUM_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_cfg = *cfg;
+  return EXSUM_OK;
+}
+
+int exsum_release(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  hipError_t first = hipSuccess;
+  for (auto &kv : g_ws) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(kv.first.first);
+    hipError_t e = hipFree(kv.second.acc);
+    if (first == hipSuccess) first = e;
+    if (kv.second.seg) {
+      e = hipFree(kv.second.seg);
+      if (first == hipSuccess) first = e;
+    }
+    (void)hipSetDevice(cur);
+  }
+  g_ws.clear();
+  return status_of(first);
+}
+
+}  // extern "C"

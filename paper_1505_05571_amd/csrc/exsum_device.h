@@ -1,0 +1,184 @@
+// exsum_device.h -- device-side building blocks of the exact sum (gfx950).
+//
+// Value model (section "Floating-point and integer formats"): a finite
+// binary64 term with bit pattern b has sign s = b>>63, exponent field
+// e = (b>>52)&2047 and mantissa field m = b & (2^52-1).  With e_eff = max(e,1)
+// and M = m + [e != 0] 2^52 its value is (-1)^s M 2^(e_eff-1075).
+//
+// Small superaccumulator (section "Exact summation using a small
+// superaccumulator"): 67 signed 64-bit chunks c_i, value sum c_i 2^(32i-1075).
+// A mantissa placed at exponent e_eff lands at chunk e_eff>>5, shifted left by
+// e_eff&31 bits, and spills into the next one or two chunks.
+//
+// Large superaccumulator (section "Faster exact summation of many terms with a
+// large superaccumulator"): 4096 chunks indexed by the top 12 bits (sign and
+// exponent) of the pattern, each holding the plain 64-bit sum of the raw bit
+// patterns added to it, plus a count of those adds.  After k <= 4096 adds the
+// sum of the mantissa fields is chunk - k*(index<<52) (mod 2^64), which is
+// below 2^64; the implicit bits add k*2^52 for normal exponents.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace exsum {
+
+constexpr int kSChunks = 67;          // small accumulator chunks
+constexpr int kLChunks = 4096;        // large accumulator chunks
+constexpr int kCap = 4096;            // raw-pattern adds one large chunk holds exactly
+
+// Merge target shared by the workgroups of one sum (or of one segment's
+// tiles).  Every field is updated with device-scope atomics and left zeroed
+// by the workgroup that finishes last, so the next call starts clean.
+struct alignas(64) GlobalAcc {
+  unsigned long long chunk[68];        // int64 two's complement sums (67 used)
+  unsigned long long pos_inf;          // nonzero if any +Inf term
+  unsigned long long neg_inf;          // nonzero if any -Inf term
+  unsigned long long nan_bits;         // max over NaN terms of (bits & ~sign)
+  unsigned int ticket;                 // workgroups finished so far
+  unsigned int pad0;
+};
+static_assert(sizeof(GlobalAcc) == 576, "GlobalAcc layout");
+
+// ---- synchronisation -------------------------------------------------------
+
+// Workgroup barrier that waits only for this wave's LDS traffic.  Global loads
+// issued ahead of the barrier (the next tile) stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// ---- wavefront reductions (all 64 lanes active) ----------------------------
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    unsigned int lo = (unsigned int)v, hi = (unsigned int)(v >> 32);
+    unsigned int olo = __shfl_xor(lo, d, 64);
+    unsigned int ohi = __shfl_xor(hi, d, 64);
+    v += ((unsigned long long)ohi << 32) | olo;
+  }
+  return v;
+}
+
+__device__ __forceinline__ long long wave_sum_i64(long long v) {
+  return (long long)wave_sum_u64((unsigned long long)v);
+}
+
+// ---- large chunk -> three small-chunk pieces -------------------------------
+
+// Chunk index ix (sign<<11 | exponent field), raw-pattern sum C of k adds.
+// Produces signed pieces for small chunks hi, hi+1, hi+2 (each |piece| < 2^32).
+__device__ __forceinline__ void chunk_pieces(unsigned int ix, unsigned long long C, unsigned int k,
+                                             long long &p0, long long &p1, long long &p2, int &hi) {
+  const unsigned int e = ix & 2047u;
+  const unsigned int e_eff = e ? e : 1u;
+  // sum of the 52-bit mantissa fields (exact: k <= 4096 keeps it below 2^64)
+  const unsigned long long T = C - (unsigned long long)k * ((unsigned long long)ix << 52);
+  const unsigned long long imp = e ? ((unsigned long long)k << 52) : 0ull;
+  const unsigned long long qlo = T + imp;           // 65-bit total mantissa sum
+  const unsigned long long qhi = qlo < T ? 1ull : 0ull;
+  const unsigned int lo = e_eff & 31u;
+  hi = (int)(e_eff >> 5);
+  const unsigned long long low64 = qlo << lo;
+  const unsigned long long top = (qhi << lo) | (lo ? (qlo >> (64 - lo)) : 0ull);
+  long long a = (long long)(low64 & 0xFFFFFFFFull);
+  long long b = (long long)(low64 >> 32);
+  long long c = (long long)top;
+  const long long neg = -(long long)(ix >> 11);      // 0 or -1
+  p0 = (a ^ neg) - neg;
+  p1 = (b ^ neg) - neg;
+  p2 = (c ^ neg) - neg;
+}
+
+// ---- one term -> two small-chunk pieces (the small-superaccumulator add) ---
+
+// For a finite term: chunk index h = e_eff>>5, low piece (< 2^32) for chunk h
+// and high piece (< 2^52) for chunk h+1, both already signed.
+__device__ __forceinline__ void term_pieces(unsigned long long b, int &h, long long &plo, long long &phi) {
+  const unsigned int e = (unsigned int)(b >> 52) & 2047u;
+  const unsigned long long M = (b & ((1ull << 52) - 1)) | ((unsigned long long)(e != 0) << 52);
+  const unsigned int e_eff = e ? e : 1u;
+  const unsigned int lo = e_eff & 31u;
+  h = (int)(e_eff >> 5);
+  const long long low = (long long)((M << lo) & 0xFFFFFFFFull);
+  const long long high = (long long)(M >> (32 - lo));
+  const long long neg = (long long)b >> 63;          // branch-free conditional negate
+  plo = (low ^ neg) - neg;
+  phi = (high ^ neg) - neg;
+}
+
+__device__ __forceinline__ bool is_special(unsigned long long b) {
+  return ((unsigned int)(b >> 32) & 0x7FF00000u) == 0x7FF00000u;
+}
+
+// Record an infinity or NaN into three 64-bit side words (LDS or global).
+__device__ __forceinline__ void note_special(unsigned long long b, unsigned long long *pos_inf,
+                                             unsigned long long *neg_inf, unsigned long long *nan_bits) {
+  if ((b & ((1ull << 52) - 1)) == 0) {
+    if (b >> 63) atomicOr(neg_inf, 1ull); else atomicOr(pos_inf, 1ull);
+  } else {
+    atomicMax(nan_bits, b & 0x7FFFFFFFFFFFFFFFull);
+  }
+}
+
+// ---- carry propagation and rounding (one thread, on a private copy) --------
+
+// Round the value sum c[i] 2^(32i-1075) (i < 67, any int64 chunks whose
+// partial sums stay in range) to binary64 bits, round to nearest, ties to
+// even.  Specials take precedence.  Serial code, run by a single lane; D is
+// caller-provided scratch of 70 words (LDS, so no private memory is used).
+__device__ inline unsigned long long round_chunks(const long long *c, unsigned long long pos_inf,
+                                                  unsigned long long neg_inf, unsigned long long nan_bits,
+                                                  unsigned int *D) {
+  if (nan_bits) return nan_bits | (1ull << 51);
+  if (pos_inf && neg_inf) return 0x7FF8000000000000ull;
+  if (pos_inf) return 0x7FF0000000000000ull;
+  if (neg_inf) return 0xFFF0000000000000ull;
+
+  // carry propagation: digits 0..65 into [0, 2^32), the rest into the top
+  long long carry = 0;
+  for (int i = 0; i < 66; i++) {
+    const long long v = c[i] + carry;
+    D[i] = (unsigned int)v;
+    carry = v >> 32;
+  }
+  long long top = c[66] + carry;                      // |top| < 2^31 for any real input
+  D[66] = (unsigned int)top;
+  D[67] = D[68] = D[69] = 0;
+  unsigned long long sign = 0;
+  if (top < 0) {                                      // magnitude by two's-complement negation
+    sign = 1ull << 63;
+    unsigned long long cy = 1;
+    for (int i = 0; i < 67; i++) {
+      const unsigned long long t = (unsigned long long)(unsigned int)~D[i] + cy;
+      D[i] = (unsigned int)t;
+      cy = t >> 32;
+    }
+  }
+  int t = 66;
+  while (t >= 0 && D[t] == 0) t--;
+  if (t < 0) return 0;                                // exact zero -> +0.0
+  // X = sum D[i] 2^(32i) in units of 2^-1075 (X is even)
+  const int B = 32 * t + 32 - __builtin_clz(D[t]);   // bit length of X
+  if (B <= 53) {                                      // denormal (or smallest normal after none)
+    const unsigned long long X = (unsigned long long)D[0] | ((unsigned long long)D[1] << 32);
+    return sign | (X >> 1);
+  }
+  const int sh = B - 53;                              // >= 1
+  const int w = sh >> 5, o = sh & 31;
+  unsigned long long q = ((unsigned long long)D[w] | ((unsigned long long)D[w + 1] << 32)) >> o;
+  if (o) q |= (unsigned long long)D[w + 2] << (64 - o);
+  q &= (1ull << 53) - 1;
+  const int rpos = sh - 1;                            // round bit position
+  const unsigned int rbit = (D[rpos >> 5] >> (rpos & 31)) & 1u;
+  unsigned int sticky = D[rpos >> 5] & ((1u << (rpos & 31)) - 1u);
+  for (int i = 0; i < (rpos >> 5); i++) sticky |= D[i];
+  unsigned long long E = (unsigned long long)sh;      // biased exponent
+  if (rbit && (sticky || (q & 1))) q += 1;
+  if (q == (1ull << 53)) { q = 1ull << 52; E += 1; }
+  if (E >= 2047) return sign | 0x7FF0000000000000ull;
+  return sign | (E << 52) | (q - (1ull << 52));
+}
+
+}  // namespace exsum

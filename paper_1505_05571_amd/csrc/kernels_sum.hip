@@ -1,0 +1,167 @@
+// kernels_sum.hip -- one exact sum per launch: the large-accumulator kernel,
+// the small-only kernel, and the inexact comparator (gfx950, wave64).
+//
+// Large kernel: workgroup b owns terms [n*b/G, n*(b+1)/G) and a private large
+// superaccumulator in LDS; it transfers every used chunk into its small
+// superaccumulator, adds that into the call's global accumulator with
+// integer atomics, and the last workgroup to finish rounds once
+// (Discussion: split the array, sum the parts exactly, add the small
+// superaccumulators, round the total).
+#include "exsum_blocks.h"
+#include "exsum_internal.h"
+
+namespace exsum {
+namespace {
+
+template <int BLOCK, int VEC>
+__global__ __launch_bounds__(BLOCK) void large_kernel(const double *__restrict__ x, long long n,
+                                                      GlobalAcc *__restrict__ g, double *__restrict__ out,
+                                                      int precombine) {
+  __shared__ LargeShared S;
+  const int tid = threadIdx.x;
+  large_init(S, tid, BLOCK);
+  __syncthreads();
+  const long long G = gridDim.x;
+  const long long r0 = n * (long long)blockIdx.x / G;
+  const long long r1 = n * (long long)(blockIdx.x + 1) / G;
+  unsigned int tile = 0;
+  accumulate_range<BLOCK, VEC>(S, x, r0, r1, precombine, tile);
+  final_flush<BLOCK, false>(S);
+  merge_and_round(S.small, S.spec, &S.ticket, S.D, g, gridDim.x, out);
+}
+
+// Small-only kernel: every wavefront sums a contiguous part into its own
+// small superaccumulator; the workgroup adds its wavefronts' accumulators
+// (each below 2^33 per chunk after the final carry step) and merges.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void small_kernel(const double *__restrict__ x, long long n,
+                                                      GlobalAcc *__restrict__ g, double *__restrict__ out) {
+  constexpr int NW = BLOCK / 64;
+  __shared__ long long s_acc[NW][68];
+  __shared__ long long s_tot[68];
+  __shared__ unsigned long long s_spec[3];
+  __shared__ unsigned int s_ticket;
+  __shared__ unsigned int s_D[70];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < NW * 68; i += BLOCK) (&s_acc[0][0])[i] = 0;
+  if (tid < 3) s_spec[tid] = 0ull;
+  __syncthreads();
+  const long long G = gridDim.x;
+  const long long r0 = n * (long long)blockIdx.x / G, r1 = n * (long long)(blockIdx.x + 1) / G;
+  const long long len = r1 - r0;
+  const long long w0 = r0 + len * wave / NW, w1 = r0 + len * (wave + 1) / NW;
+  small_wave_accumulate(s_acc[wave], s_spec, x, w0, w1, lane);
+  __syncthreads();
+  if (tid < 68) {
+    long long t = 0;
+#pragma unroll
+    for (int w = 0; w < NW; w++) t += s_acc[w][tid];
+    s_tot[tid] = t;
+  }
+  merge_and_round(s_tot, s_spec, &s_ticket, s_D, g, gridDim.x, out);
+}
+
+// Inexact comparator: ordinary binary64 additions per thread (2*VEC
+// independent accumulators), then wave, block and a fixed-order tree over the
+// per-workgroup partials in the last workgroup.
+template <int BLOCK, int VEC>
+__global__ __launch_bounds__(BLOCK) void inexact_kernel(const double *__restrict__ x, long long n,
+                                                        double *__restrict__ partials,
+                                                        unsigned int *__restrict__ ticket,
+                                                        double *__restrict__ out) {
+  __shared__ double s_red[BLOCK / 64];
+  __shared__ unsigned int s_ticket;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const long long G = gridDim.x;
+  const long long r0 = n * (long long)blockIdx.x / G, r1 = n * (long long)(blockIdx.x + 1) / G;
+  double a[2 * VEC];
+#pragma unroll
+  for (int j = 0; j < 2 * VEC; j++) a[j] = 0.0;
+  if (r1 > r0) {
+    const long long head = (reinterpret_cast<uintptr_t>(x + r0) & 15) ? 1 : 0;
+    const long long s0 = r0 + head;
+    const long long nv = (r1 - s0) >> 1;
+    if (tid == 0 && head) a[0] += x[r0];
+    if (tid == 1 && ((r1 - s0) & 1)) a[1] += x[r1 - 1];
+    const double2 *__restrict__ xv = reinterpret_cast<const double2 *>(x + s0);
+    constexpr int TILE_V = BLOCK * VEC;
+    long long base = 0;
+    for (; base + TILE_V <= nv; base += TILE_V) {
+      double2 v[VEC];
+#pragma unroll
+      for (int j = 0; j < VEC; j++) v[j] = xv[base + j * BLOCK + tid];
+#pragma unroll
+      for (int j = 0; j < VEC; j++) { a[2 * j] += v[j].x; a[2 * j + 1] += v[j].y; }
+    }
+    for (long long i = base + tid; i < nv; i += BLOCK) { a[0] += xv[i].x; a[1] += xv[i].y; }
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < 2 * VEC; j++) s += a[j];
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
+  if (lane == 0) s_red[wave] = s;
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int w = 0; w < BLOCK / 64; w++) t += s_red[w];
+    partials[blockIdx.x] = t;
+    __threadfence();
+    s_ticket = atomicAdd(ticket, 1u);
+  }
+  __syncthreads();
+  if (s_ticket != gridDim.x - 1) return;
+  __threadfence();
+  double t = 0.0;
+  for (long long i = tid; i < G; i += BLOCK) {
+    t += __longlong_as_double((long long)__hip_atomic_load((unsigned long long *)&partials[i], __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT));
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) t += __shfl_xor(t, d, 64);
+  __syncthreads();
+  if (lane == 0) s_red[wave] = t;
+  __syncthreads();
+  if (tid == 0) {
+    double r = 0.0;
+    for (int w = 0; w < BLOCK / 64; w++) r += s_red[w];
+    out[0] = r;
+    atomicExch(ticket, 0u);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_large(const double *x, int64_t n, GlobalAcc *g, double *out, hipStream_t s, int block,
+                        int vec, int grid, int precombine) {
+  if (grid < 1) grid = 1;
+#define EXSUM_LARGE_CASE(B, V)                                                                   \
+  if (block == B && vec == V) {                                                                  \
+    hipLaunchKernelGGL((large_kernel<B, V>), dim3(grid), dim3(B), 0, s, x, (long long)n, g, out, \
+                       precombine);                                                              \
+    return hipGetLastError();                                                                    \
+  }
+  EXSUM_LARGE_CASE(256, 2)
+  EXSUM_LARGE_CASE(256, 4)
+  EXSUM_LARGE_CASE(256, 6)
+  EXSUM_LARGE_CASE(512, 2)
+  EXSUM_LARGE_CASE(512, 3)
+#undef EXSUM_LARGE_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_small(const double *x, int64_t n, GlobalAcc *g, double *out, hipStream_t s, int grid) {
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL((small_kernel<256>), dim3(grid), dim3(256), 0, s, x, (long long)n, g, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_inexact(const double *x, int64_t n, double *partials, unsigned int *ticket, double *out,
+                          hipStream_t s, int grid) {
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL((inexact_kernel<256, 4>), dim3(grid), dim3(256), 0, s, x, (long long)n, partials,
+                     ticket, out);
+  return hipGetLastError();
+}
+
+}  // namespace exsum

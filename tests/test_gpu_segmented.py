@@ -1,0 +1,110 @@
+"""GPU parity of the segmented (batched) exact sums against the oracle, bit
+for bit, for several small/large thresholds and tile sizes."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1505_05571_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ex():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1505_05571_amd as ex
+    ex.load_library()
+    yield ex
+    ex.exsum_set_config(DEFAULT[0])
+
+
+DEFAULT = []
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def seg_bits(ex, xt, offt, **kw):
+    if not DEFAULT:
+        DEFAULT.append(ex.exsum_get_config())
+    c = ex.exsum_get_config()
+    base = DEFAULT[0]
+    for k, _ in c._fields_:
+        setattr(c, k, getattr(base, k))
+    for k, v in kw.items():
+        setattr(c, k, v)
+    ex.exsum_set_config(c)
+    out = ex.exsum_segmented_f64(xt, offt)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().view(np.uint64)
+
+
+VARIANTS = [
+    dict(),
+    dict(seg_small_max=0, seg_tile=4096),
+    dict(seg_small_max=65536, seg_tile=8192),
+    dict(seg_small_max=100, seg_tile=65536, seg_grid=5),
+    dict(seg_small_max=2048, seg_tile=4096 * 3, seg_grid=1),
+]
+
+
+def test_mixed_lengths(ex):
+    x, off = W.segments(nseg=3000, seed=1, hi=300000)
+    want = oracle.segmented_f64(x, off)
+    xt, offt = dev(x), dev(off)
+    for v in VARIANTS:
+        got = seg_bits(ex, xt, offt, **v)
+        assert np.array_equal(got, want), v
+
+
+def test_empty_and_tiny_segments(ex):
+    rng = np.random.default_rng(2)
+    L = rng.choice([0, 0, 1, 2, 3, 64, 65, 5000, 70000], size=2000)
+    off = np.zeros(L.size + 1, dtype=np.int64)
+    np.cumsum(L, out=off[1:])
+    x = W.uniform_exponent(int(off[-1]), seed=2)
+    want = oracle.segmented_f64(x, off)
+    xt, offt = dev(x), dev(off)
+    for v in VARIANTS:
+        assert np.array_equal(seg_bits(ex, xt, offt, **v), want), v
+
+
+def test_offsets_not_starting_at_zero_and_specials(ex):
+    x = W.uniform_exponent(400000, seed=3)
+    x[[10, 20000, 300001]] = [np.inf, np.nan, -np.inf]
+    off = np.array([7, 7, 11, 25000, 25001, 300000, 300002, 399999], dtype=np.int64)
+    want = oracle.segmented_f64(x, off)
+    xt, offt = dev(x), dev(off)
+    for v in VARIANTS:
+        assert np.array_equal(seg_bits(ex, xt, offt, **v), want), v
+
+
+def test_hot_chunk_segments(ex):
+    rng = np.random.default_rng(4)
+    f = rng.integers(0, 1 << 52, size=1 << 20, dtype=np.uint64)
+    x = ((np.uint64(0x3FF) << np.uint64(52)) | f).view(np.float64)
+    off = np.array([0, 1000, 300000, 300001, 1 << 20], dtype=np.int64)
+    want = oracle.segmented_f64(x, off)
+    xt, offt = dev(x), dev(off)
+    for v in VARIANTS:
+        assert np.array_equal(seg_bits(ex, xt, offt, **v), want), v
+
+
+def test_repeated_calls_and_shrinking_batches(ex):
+    x, off = W.segments(nseg=5000, seed=5, hi=100000)
+    xt = dev(x)
+    for nseg in (5000, 17, 4999, 1):
+        o = off[:nseg + 1]
+        want = oracle.segmented_f64(x, o)
+        assert np.array_equal(seg_bits(ex, xt, dev(o)), want), nseg
+
+
+def test_full_size_batched_workload(ex):
+    # 65536 segments, lognormal lengths (median 1000, sigma 2), default config
+    x, off = W.segments(nseg=65536, seed=0)
+    want = oracle.segmented_f64(x, off)
+    got = seg_bits(ex, dev(x), dev(off))
+    assert np.array_equal(got, want)

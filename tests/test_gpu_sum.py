@@ -1,0 +1,235 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle, bit
+for bit (0 ulp), on seeded inputs of the benchmark's shapes plus edge cases.
+Every launch configuration must give the same bits."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1505_05571_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ex():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1505_05571_amd as ex
+    ex.load_library()
+    return ex
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def gbits(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().view(np.uint64)
+
+
+def run(ex, x, cfg=None):
+    xt = dev(x) if isinstance(x, np.ndarray) else x
+    out = ex.exsum_f64(xt) if cfg is None else ex.exsum_f64_cfg(xt, cfg)
+    return int(gbits(out)[0])
+
+
+def cfg_with(ex, **kw):
+    c = ex.exsum_get_config()
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+LARGE_VARIANTS = [
+    dict(large_block=256, large_vec=4, precombine=16),
+    dict(large_block=256, large_vec=2, precombine=0),
+    dict(large_block=256, large_vec=6, precombine=1),
+    dict(large_block=512, large_vec=2, precombine=32),
+    dict(large_block=512, large_vec=3, precombine=8),
+]
+
+
+def all_paths(ex):
+    """Small-only path and several large-path configurations (and grids)."""
+    cfgs = [cfg_with(ex, small_max=10 ** 12)]
+    for v in LARGE_VARIANTS:
+        for grid in (0, 1, 7, 300):
+            cfgs.append(cfg_with(ex, small_max=0, large_grid=grid, **v))
+    return cfgs
+
+
+def test_small_normal_1000(ex):
+    x = W.small_normal(1000, seed=0)
+    want = int(oracle.sum_f64(x))
+    assert run(ex, x) == want
+    for c in all_paths(ex):
+        assert run(ex, x, c) == want
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 31, 64, 65, 127, 1000, 2047, 2048, 2049, 4095, 4096, 4097,
+                               10000, 65537, 262147, 1000003])
+def test_sizes_and_paths(ex, n):
+    for gen in (lambda m: W.uniform_exponent(m, seed=n), lambda m: W.small_normal(m, seed=n + 1)):
+        x = gen(n)
+        want = int(oracle.sum_f64(x))
+        assert run(ex, x) == want, n
+        if n <= 70000:
+            for c in all_paths(ex):
+                assert run(ex, x, c) == want, (n, c.as_dict())
+
+
+def test_misaligned_slices(ex):
+    x = W.uniform_exponent(300001, seed=9)
+    xt = dev(x)
+    for lo, hi in [(1, 300001), (3, 299998), (1, 2), (5, 6), (7, 100000), (0, 299999)]:
+        want = int(oracle.sum_f64(x[lo:hi]))
+        assert run(ex, xt[lo:hi]) == want
+        for c in all_paths(ex)[:6]:
+            assert run(ex, xt[lo:hi], c) == want
+
+
+def test_random_bit_patterns(ex):
+    for seed in range(6):
+        x = W.random_bits(200000 + seed, seed=seed)
+        want = int(oracle.sum_f64(x))
+        for c in all_paths(ex)[:8]:
+            assert run(ex, x, c) == want
+
+
+def test_hot_chunk_many_tiles(ex):
+    # every term in one (sign, exponent) chunk: counts cross the transfer
+    # threshold over and over; pre-combine on and off must agree
+    rng = np.random.default_rng(3)
+    f = rng.integers(0, 1 << 52, size=1 << 20, dtype=np.uint64)
+    x = ((np.uint64(0x3FF) << np.uint64(52)) | f).view(np.float64)
+    want = int(oracle.sum_f64(x))
+    for c in all_paths(ex):
+        assert run(ex, x, c) == want
+    xneg = -x
+    assert run(ex, xneg) == int(oracle.sum_f64(xneg))
+
+
+def test_adversarial_small_scale(ex):
+    for ovf in (False, True):
+        x = W.adversarial(1 << 18, seed=4, overflow=ovf)
+        want = int(oracle.sum_f64(x))
+        if ovf:
+            assert want == 0x7FF0000000000000
+        for c in all_paths(ex)[:10]:
+            assert run(ex, x, c) == want
+
+
+def test_mirrored_is_zero(ex):
+    for n in (10, 1001, 100000, 1000001):
+        x = W.mirrored(n, seed=n)
+        assert run(ex, x) == 0
+        assert run(ex, np.random.default_rng(n).permutation(x)) == 0
+
+
+def test_worked_example_and_closed_forms(ex):
+    dmax = np.finfo(np.float64).max
+    cases = [
+        ([1e15, -1e15, 0.1], 0x3FB999999999999A),
+        ([dmax, 2.0 ** 970], 0x7FF0000000000000),
+        ([dmax, 2.0 ** 970, -5e-324], int(np.array([dmax]).view(np.uint64)[0])),
+        ([2.0 ** 1023, 2.0 ** 1023, -(2.0 ** 1023)], int(np.array([2.0 ** 1023]).view(np.uint64)[0])),
+        ([-0.0, -0.0], 0),
+        ([], 0),
+        ([5e-324] * 3, 3),
+    ]
+    for vals, want in cases:
+        x = np.array(vals, dtype=np.float64)
+        assert int(oracle.sum_f64(x)) == want
+        for c in all_paths(ex)[:6]:
+            assert run(ex, x, c) == want, vals
+    # the same closed forms buried in a long array of cancelling pairs
+    rng = np.random.default_rng(5)
+    pairs = np.ldexp(rng.standard_normal(200000), rng.integers(-900, 900, size=200000))
+    for vals, want in cases[:4]:
+        x = np.concatenate([pairs, -pairs, np.array(vals)])
+        rng.shuffle(x)
+        assert int(oracle.sum_f64(x)) == want
+        for c in all_paths(ex)[:6]:
+            assert run(ex, x, c) == want
+
+
+def test_special_values_anywhere(ex):
+    rng = np.random.default_rng(6)
+    base = W.uniform_exponent(100000, seed=6)
+    nan_a = np.array([0x7FF0000000000001], dtype=np.uint64).view(np.float64)[0]
+    nan_b = np.array([0xFFF80000000ABCDE], dtype=np.uint64).view(np.float64)[0]
+    for specials in ([math.inf], [-math.inf], [math.inf, -math.inf], [nan_a], [nan_a, nan_b, math.inf]):
+        x = base.copy()
+        pos = rng.choice(x.size, size=len(specials), replace=False)
+        x[pos] = specials
+        want = int(oracle.sum_f64(x))
+        for c in all_paths(ex)[:8]:
+            assert run(ex, x, c) == want, specials
+
+
+def test_denormals_and_extremes(ex):
+    rng = np.random.default_rng(7)
+    b = rng.integers(0, 1 << 53, size=300000, dtype=np.uint64)
+    s = rng.integers(0, 2, size=300000, dtype=np.uint64) << np.uint64(63)
+    x = (b | s).view(np.float64)
+    want = int(oracle.sum_f64(x))
+    for c in all_paths(ex)[:8]:
+        assert run(ex, x, c) == want
+    top = ((np.uint64(0x7FE) << np.uint64(52)) | rng.integers(0, 1 << 52, size=100000, dtype=np.uint64)).view(np.float64)
+    top = np.concatenate([top, -top[:99990]])
+    want = int(oracle.sum_f64(top))
+    for c in all_paths(ex)[:8]:
+        assert run(ex, top, c) == want
+
+
+def test_permutation_invariance(ex):
+    x = W.uniform_exponent(500000, seed=8)
+    want = int(oracle.sum_f64(x))
+    rng = np.random.default_rng(8)
+    for _ in range(3):
+        assert run(ex, rng.permutation(x)) == want
+
+
+def test_repeated_calls_leave_workspace_clean(ex):
+    xs = [W.uniform_exponent(n, seed=n) for n in (5000, 700000, 3, 123456)]
+    wants = [int(oracle.sum_f64(x)) for x in xs]
+    for _ in range(3):
+        for x, w in zip(xs, wants):
+            assert run(ex, x) == w
+
+
+def test_inexact_comparator_is_close(ex):
+    x = W.small_normal(1000003, seed=3)
+    exact = oracle.bits_to_f64(oracle.sum_f64(x))
+    got = float(ex.exsum_inexact_f64(dev(x)).cpu()[0])
+    assert abs(got - exact) <= 1e-9 * np.abs(x).sum()
+
+
+def test_bad_arguments(ex):
+    import ctypes
+    lib = ex.load_library()
+    assert lib.exsum_f64(None, 5, None, None) == 1
+    assert lib.exsum_f64(None, -1, None, None) == 1
+    assert lib.exsum_segmented_f64(None, None, -1, None, None) == 1
+
+
+@pytest.mark.parametrize("which", ["uniform_exponent_1e8"])
+def test_full_size_uniform_exponent(ex, which):
+    # the benchmark workload at full size, in its default launch configuration
+    x = W.uniform_exponent(10 ** 8, seed=0)
+    want = int(oracle.sum_f64_mt(x, 8))
+    xt = dev(x)
+    assert run(ex, xt) == want
+    assert run(ex, xt) == want
+
+
+def test_full_size_adversarial(ex):
+    for ovf in (False, True):
+        x = W.adversarial(1 << 27, seed=0, overflow=ovf)
+        want = int(oracle.sum_f64_mt(x, 8))
+        assert run(ex, dev(x)) == want
