@@ -1,0 +1,265 @@
+#!/usr/bin/env python3
+"""Benchmark of the exact binary64 sum on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME]
+
+One step is one call of ``exsum_f64`` over the whole input: load, large
+superaccumulator in LDS, transfers to the small superaccumulator, integer
+merge across workgroups and the final rounding -- the complete path.  The
+default workload is 10^8 binary64 terms (800 MB) with sign uniform, mantissa
+uniform in [1, 2) and exponent uniform in [-300, 300], resident in HBM before
+the timed region starts.  Prints ONE JSON line.
+
+Besides the throughput, the line carries:
+  * ``roofline``: the large-accumulator kernel's algorithmic bytes (8 per
+    term) over its average duration, measured with HIP events on the stream
+    it runs on, against the 8 TB/s HBM peak; ``traffic`` is the HBM bytes per
+    launch from rocprofv3 counters (profiles/) when they were taken on the
+    current kernel source, else null;
+  * ``inexact``: the same data summed by an ordinary (inexact) HIP tree sum
+    and by torch.sum, and the time ratio exact/inexact;
+  * ``cpu_baseline``: the CPU oracle (plain wide-integer sum) timed on the
+    host cores on the same array;
+  * ``parity``: whether the GPU bits equal the oracle's.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_1505_05571_amd/csrc/kernels_sum.hip", "paper_1505_05571_amd/csrc/exsum_blocks.h",
+                  "paper_1505_05571_amd/csrc/exsum_device.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "large_kernel_uniform_exponent_1e8_traffic.json")
+
+WORKLOADS = {
+    "uniform_exponent": "uniform_exponent n=1e8 (800 MB binary64; sign uniform, mantissa [1,2), exponent [-300,300])",
+    "adversarial": "adversarial n=2^27 (1.07 GB binary64; hot chunk half, cancelling pairs, tiny terms, 1% near DBL_MAX)",
+    "small_normal": "small_normal n=1000 (sign uniform, |N(0,1)| 2^k, k in [-20,20]); latency",
+    "segments": "segments nseg=65536 lognormal(median 1000, sigma 2) clipped [1,1e6]; one batched call",
+    "copy": "device-to-device copy of 800 MB (reference for HBM bandwidth and counter calibration)",
+}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def read_traffic():
+    """HBM bytes per launch from committed counter summaries, if they were
+    taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def make_input(name: str):
+    from paper_1505_05571_amd import workloads as W
+    if name == "uniform_exponent":
+        return W.uniform_exponent(10 ** 8, seed=0), None
+    if name == "adversarial":
+        return W.adversarial(1 << 27, seed=0), None
+    if name == "small_normal":
+        return W.small_normal(1000, seed=0), None
+    if name == "segments":
+        return W.segments(nseg=65536, seed=0)
+    if name == "copy":
+        return W.uniform_exponent(10 ** 8, seed=0), None
+    raise ValueError(name)
+
+
+def cpu_baseline(x, offsets, budget_s: float = 10.0):
+    """Time the oracle (as it stands) on the host cores."""
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    reps, t0 = 0, time.perf_counter()
+    if offsets is None:
+        while True:
+            oracle.sum_f64_mt(x, cores)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s or reps >= 50:
+                break
+        return {"value": round(8.0 * x.size * reps / el / 1e9, 4), "unit": "GB/s", "cores": cores,
+                "kind": "oracle",
+                "sample": "the full %d-term input, %d repetition(s), split over %d threads, exact merge"
+                          % (x.size, reps, cores)}
+    # segmented: single-threaded oracle over a bounded prefix of the segments
+    nseg = offsets.size - 1
+    k, t0 = 0, time.perf_counter()
+    terms = 0
+    step = 512
+    while k < nseg:
+        hi = min(k + step, nseg)
+        oracle.segmented_f64(x, offsets[k:hi + 1])
+        terms += int(offsets[hi] - offsets[k])
+        k = hi
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    el = time.perf_counter() - t0
+    return {"value": round(8.0 * terms / el / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d of %d segments (%d terms), one thread" % (k, nseg, terms)}
+
+
+def copy_reference(torch, dev, x, args):
+    """Plain device copy of the same bytes: the achievable HBM rate, and the
+    reference kernel (known read and write bytes) for counter calibration."""
+    src = torch.from_numpy(x).to(dev)
+    dst = torch.empty_like(src)
+    for _ in range(args.warmup):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    e.record()
+    torch.cuda.synchronize()
+    t = s.elapsed_time(e) / 1e3 / args.steps
+    print(json.dumps({"workload": WORKLOADS["copy"], "bytes_read_per_copy": 8 * x.size,
+                      "bytes_written_per_copy": 8 * x.size, "ms_per_copy": round(t * 1e3, 4),
+                      "read_plus_write_GBs": round(16.0 * x.size / t / 1e9, 1)}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="uniform_exponent", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build measures one GPU only; --gpus %d (WORLD_SIZE=%d) is not supported. "
+              "How the exact sum would shard across GPUs is described in DESIGN.md." % (args.gpus, world),
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1505_05571_amd as ex
+    ex.load_library()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    x, offsets = make_input(args.workload)
+    n = int(x.size)
+    if args.workload == "copy":
+        return copy_reference(torch, dev, x, args)
+    # two resident copies, alternated, so no step re-reads data cached by the previous one
+    bufs = [torch.from_numpy(x).to(dev), torch.from_numpy(x).to(dev)]
+    off_t = torch.from_numpy(offsets).to(dev) if offsets is not None else None
+    out = torch.empty(max(1, (offsets.size - 1) if offsets is not None else 1), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(i):
+        if off_t is None:
+            ex.exsum_f64(bufs[i & 1], out=out, stream=stream)
+        else:
+            ex.exsum_segmented_f64(bufs[i & 1], off_t, out=out, stream=stream)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+
+    # timed region: exactly K steps, each bracketed by events on the kernel's stream
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record(stream)
+        step(i)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+
+    # parity of the timed result against the oracle
+    import oracle
+    gpu_bits = out.cpu().numpy().view(np.uint64)
+    if offsets is None:
+        want = np.array([oracle.sum_f64_mt(x, len(os.sched_getaffinity(0)))], dtype=np.uint64)
+        parity = bool(gpu_bits[0] == want[0])
+    else:
+        want = oracle.segmented_f64(x, offsets)
+        parity = bool(np.array_equal(gpu_bits[:want.size], want))
+
+    bytes_per_step = 8.0 * n
+    value = bytes_per_step * args.steps / wall / 1e9
+    avg_kernel_s = float(ev_ms.mean()) / 1e3
+    achieved = bytes_per_step / avg_kernel_s / 1e9
+    traffic = read_traffic() if args.workload == "uniform_exponent" else None
+
+    # inexact comparators on the same data (same rotation)
+    def time_fn(fn, reps):
+        for i in range(3):
+            fn(i)
+        torch.cuda.synchronize()
+        s = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        s.record(stream)
+        for i in range(reps):
+            fn(i)
+        e.record(stream)
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) / 1e3 / reps
+
+    inexact = None
+    if off_t is None:
+        t_hip = time_fn(lambda i: ex.exsum_inexact_f64(bufs[i & 1], out=out, stream=stream), 20)
+        t_torch = time_fn(lambda i: torch.sum(bufs[i & 1]), 20)
+        t_min = min(t_hip, t_torch)
+        inexact = {"hip_tree_sum_GBs": round(bytes_per_step / t_hip / 1e9, 1),
+                   "torch_sum_GBs": round(bytes_per_step / t_torch / 1e9, 1),
+                   "exact_over_inexact_time": round(avg_kernel_s / t_min, 3)}
+
+    result = {
+        "metric": "exact-sum GB/s (0-ulp vs oracle) and % of HBM peak vs inexact GPU sum",
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload], "n_terms": n, "input_dtype": "f64", "seed": 0,
+                   "terms_per_s": round(n * args.steps / wall, 1)},
+        "latency_ms": {"p50": round(float(np.percentile(ev_ms, 50)), 4),
+                       "p99": round(float(np.percentile(ev_ms, 99)), 4)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
+        "inexact": inexact,
+        "parity": parity,
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(x, offsets)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

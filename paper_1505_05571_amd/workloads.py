@@ -89,13 +89,12 @@ def adversarial(n: int = 1 << 27, seed: int = 0, overflow: bool = False) -> np.n
     tiny_mask = (i % 1000) == 999
     ntiny = int(tiny_mask.sum())
     rest = half - ntiny
-    assert rest % 2 == 0
-    npairs = rest // 2
+    npairs = rest // 2                     # an odd leftover slot (small n only) holds +0.0
     t = np.ldexp(rng.standard_normal(ntiny), -60)
     x = np.ldexp(rng.standard_normal(npairs), 40)
-    pairs = np.empty(rest, dtype=np.float64)
-    pairs[0::2] = x
-    pairs[1::2] = -x
+    pairs = np.zeros(rest, dtype=np.float64)
+    pairs[0:2 * npairs:2] = x
+    pairs[1:2 * npairs:2] = -x
 
     nbig = (n // 100) & ~1
     nbig_pairs = nbig // 2
