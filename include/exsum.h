@@ -106,10 +106,18 @@ int exsum_inexact_f64(const double *x, int64_t n, double *out, void *stream);
 /*
  * Launch configuration of the exact sum (tuning and testing).  Every field
  * changes only speed, never a result bit.
- *   large_block : threads per workgroup of the large-accumulator kernel
- *                 (256 or 512).
- *   large_vec   : 16-byte loads per thread per tile (2, 4 or 8).
- *   large_grid  : workgroups of the large kernel; 0 = 3 per compute unit.
+ *   large_block : threads per workgroup of the large-accumulator kernel.
+ *   large_vec   : 16-byte loads per thread per tile.
+ *   large_depth : tiles of loads kept in flight per thread.
+ *   large_mode  : when a large-accumulator chunk is transferred to the small
+ *                 one.  0 = by count (the paper's rule: raw bit patterns are
+ *                 added and a count per chunk triggers the transfer); 1 = by
+ *                 carry (mantissas with their implicit bit are added and the
+ *                 LDS add that wraps a chunk past 2^64 forwards the carry).
+ *                 Built (block, vec, depth, mode): (256,6,3,0) (256,4,3,0)
+ *                 (256,2,4,0) (512,3,2,0) (512,2,2,0) (256,4,3,1) (512,4,2,1)
+ *                 (512,2,4,1) (1024,2,2,1) (1024,4,2,1).
+ *   large_grid  : workgroups of the large kernel; 0 = one per compute unit.
  *   precombine  : lanes of a wavefront that must share one (sign, exponent)
  *                 chunk before they are first summed across the wavefront and
  *                 added with a single LDS update; 0 disables the pre-combine.
@@ -122,6 +130,8 @@ int exsum_inexact_f64(const double *x, int64_t n, double *out, void *stream);
 typedef struct {
     int32_t large_block;
     int32_t large_vec;
+    int32_t large_depth;
+    int32_t large_mode;
     int32_t large_grid;
     int32_t precombine;
     int64_t small_max;

@@ -42,6 +42,8 @@ class ExsumConfig(ctypes.Structure):
     _fields_ = [
         ("large_block", ctypes.c_int32),
         ("large_vec", ctypes.c_int32),
+        ("large_depth", ctypes.c_int32),
+        ("large_mode", ctypes.c_int32),
         ("large_grid", ctypes.c_int32),
         ("precombine", ctypes.c_int32),
         ("small_max", ctypes.c_int64),

@@ -19,8 +19,10 @@ std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
 
 exsum_config default_config() {
   exsum_config c;
-  c.large_block = 256;
+  c.large_block = 512;
   c.large_vec = 4;
+  c.large_depth = 2;
+  c.large_mode = 1;
   c.large_grid = 0;
   c.precombine = 16;
   c.small_max = 4096;
@@ -35,15 +37,11 @@ exsum_config g_cfg = default_config();
 int g_cu[64] = {0};
 
 constexpr int64_t kMaxN = int64_t(1) << 40;
-constexpr int kMaxGrid = 8192;
-
-bool valid_large(int block, int vec) {
-  return (block == 256 && (vec == 2 || vec == 4 || vec == 6)) || (block == 512 && (vec == 2 || vec == 3));
-}
 
 bool config_ok(const exsum_config &c) {
-  if (!valid_large(c.large_block, c.large_vec)) return false;
+  if (!large_variant_exists(c.large_block, c.large_vec, c.large_depth, c.large_mode)) return false;
   if (c.large_grid < 0 || c.large_grid > kMaxGrid) return false;
+  if (c.small_grid > kMaxGrid) return false;
   if (c.precombine < 0 || c.precombine > 64) return false;
   if (c.small_max < 0 || c.small_grid < 0 || c.small_grid > kMaxGrid) return false;
   if (c.seg_grid < 0 || c.seg_grid > kMaxGrid) return false;
@@ -83,14 +81,15 @@ int get_workspace(hipStream_t s, Workspace **out, int *dev_out) {
     Workspace w;
     w.max_grid = kMaxGrid;
     void *p = nullptr;
-    const size_t bytes = kGlobalAccBytes + sizeof(double) * kMaxGrid + 256;
+    const size_t mb = (merge_rows_bytes() + 255) / 256 * 256;
+    const size_t bytes = mb + sizeof(double) * kMaxGrid + 256;
     e = hipMalloc(&p, bytes);
     if (e != hipSuccess) return status_of(e);
     e = hipMemset(p, 0, bytes);
     if (e != hipSuccess) { (void)hipFree(p); return status_of(e); }
-    w.acc = reinterpret_cast<GlobalAcc *>(p);
-    w.partials = reinterpret_cast<double *>(static_cast<char *>(p) + kGlobalAccBytes);
-    w.ticket = reinterpret_cast<unsigned int *>(static_cast<char *>(p) + kGlobalAccBytes + sizeof(double) * kMaxGrid);
+    w.rows = reinterpret_cast<MergeRows *>(p);
+    w.partials = reinterpret_cast<double *>(static_cast<char *>(p) + mb);
+    w.ticket = reinterpret_cast<unsigned int *>(static_cast<char *>(p) + mb + sizeof(double) * kMaxGrid);
     it = g_ws.emplace(key, w).first;
   }
   *out = &it->second;
@@ -109,15 +108,17 @@ int run_sum(const double *x, int64_t n, double *out, hipStream_t s, const exsum_
   if (n <= c.small_max) {
     int grid = c.small_grid;
     if (grid == 0) grid = (int)std::min<int64_t>(std::max<int64_t>((n + 8191) / 8192, 1), 64);
-    e = launch_small(x, n, w->acc, out, s, grid);
+    e = launch_small(x, n, w->rows, out, s, grid);
   } else {
     int grid = c.large_grid;
     if (grid == 0) {
+      // one workgroup per compute unit, each with at least a few tiles
       const int64_t tile_terms = int64_t(2) * c.large_block * c.large_vec;
       const int64_t want = (n + 4 * tile_terms - 1) / (4 * tile_terms);
-      grid = (int)std::min<int64_t>(std::max<int64_t>(want, 1), int64_t(3) * cu_count(dev));
+      grid = (int)std::min<int64_t>(std::max<int64_t>(want, 1), int64_t(cu_count(dev)));
     }
-    e = launch_large(x, n, w->acc, out, s, c.large_block, c.large_vec, grid, c.precombine);
+    e = launch_large(x, n, w->rows, out, s, c.large_block, c.large_vec, c.large_depth, c.large_mode, grid,
+                     c.precombine);
   }
   return status_of(e);
 }
@@ -235,7 +236,7 @@ int exsum_release(void) {
     int cur = 0;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(kv.first.first);
-    hipError_t e = hipFree(kv.second.acc);
+    hipError_t e = hipFree(kv.second.rows);
     if (first == hipSuccess) first = e;
     if (kv.second.seg) {
       e = hipFree(kv.second.seg);

@@ -3,38 +3,57 @@
 //
 // Large-accumulator body (section "Faster exact summation of many terms with a
 // large superaccumulator"), re-planned for a GPU workgroup:
-//   * the workgroup owns one large superaccumulator in LDS: 4096 raw-pattern
-//     chunks (32 KiB) and 4096 32-bit counts (16 KiB);
-//   * terms arrive by coalesced 16-byte loads, the next tile's loads issued
-//     before the current tile is added;
-//   * a term is one 64-bit LDS add of its whole bit pattern to the chunk its
-//     top 12 bits (sign and exponent) select, and one count add -- no mask,
-//     no sign test, no mantissa split;
-//   * lanes of a wavefront that share a chunk are summed across the wave
-//     first, so one lane updates a hot chunk once instead of 64 times;
-//   * the paper's per-add count check becomes a threshold: the add that lifts
-//     a count to THR = 4096 - (terms per tile) marks the chunk, and marked
-//     chunks are transferred to the small superaccumulator at the next tile
+//   * the workgroup owns one large superaccumulator in LDS: 4096 chunks, one
+//     per (sign, exponent) combination, indexed by the top 12 bits of a term;
+//   * terms arrive by coalesced 16-byte loads with the next DEPTH tiles in
+//     flight; a term costs one 64-bit LDS add to the chunk it selects;
+//   * lanes of a wavefront whose whole tile lands in one chunk are summed
+//     across the wave first, so a hot chunk takes one update per tile;
+//   * chunks reach the workgroup's small superaccumulator (67 chunks, LDS)
+//     before a 64-bit chunk could lose information, and at the end every used
+//     chunk is transferred, grouped by the top six exponent bits so one
+//     wavefront reduction serves 64 chunks.
+//
+// Two ways of deciding when a chunk must be transferred (template MODE):
+//   kCountMode -- the paper's: a chunk holds the plain sum of raw bit
+//     patterns and a count of its adds; after k <= 4096 adds the mantissa sum
+//     is chunk - k*(index<<52).  On the GPU the per-add count check becomes a
+//     threshold: the add that lifts a count to THR = 4096 - (terms per tile)
+//     marks the chunk, and marked chunks are transferred at the next tile
 //     barrier.  Between barriers a chunk gains at most one tile of adds, so no
-//     chunk ever holds more than 4095 adds and its mantissa sum stays exact;
-//   * at the end every used chunk is transferred, grouped by the top six
-//     exponent bits so one wavefront reduction serves 64 chunks.
+//     chunk ever holds more than 4095 adds.
+//   kCarryMode -- GPU-native: a chunk holds the sum of the 53-bit mantissas
+//     (implicit bit included, so no correction is ever needed) modulo 2^64.
+//     The LDS add returns the chunk's previous value, so the lane whose add
+//     wraps past 2^64 sees it and adds the lost 2^64 units directly to the
+//     small superaccumulator (+-2^(e_eff&31) at small chunk (e_eff>>5)+2).
+//     No counts, no thresholds and no tile barriers: waves run independently
+//     and a tile may hold any number of terms.
 #pragma once
 
 #include "exsum_device.h"
 
 namespace exsum {
 
+constexpr int kCountMode = 0;
+constexpr int kCarryMode = 1;
+
 __device__ __forceinline__ unsigned long long as_bits(double v) {
   return (unsigned long long)__double_as_longlong(v);
+}
+
+// 53-bit mantissa of a finite term with its implicit bit (none for e == 0).
+__device__ __forceinline__ unsigned long long mantissa53(unsigned long long b) {
+  const unsigned int e = (unsigned int)(b >> 52) & 2047u;
+  return (b & ((1ull << 52) - 1)) | ((unsigned long long)(e != 0u) << 52);
 }
 
 // ---------------------------------------------------------------------------
 // LDS state of the large-accumulator body
 // ---------------------------------------------------------------------------
 struct LargeShared {
-  unsigned long long chunk[kLChunks];   // raw-pattern sums
-  unsigned int cnt[kLChunks];           // adds since the last transfer
+  unsigned long long chunk[kLChunks];   // raw-pattern sums (count mode) or mantissa sums (carry mode)
+  unsigned int cnt[kLChunks];           // adds since the last transfer (count mode)
   long long small[68];                  // the workgroup's small accumulator
   unsigned int flushbits[kLChunks / 32];
   unsigned long long spec[3];           // +Inf seen, -Inf seen, max NaN bits
@@ -59,7 +78,7 @@ __device__ __forceinline__ void mark_chunk(LargeShared &S, unsigned int ix, unsi
   S.flag[tile % 3] = 1u;
 }
 
-// Transfer chunk ix into the small accumulator and reset it.
+// Count mode: transfer chunk ix into the small accumulator and reset it.
 __device__ __forceinline__ void flush_chunk(LargeShared &S, unsigned int ix) {
   const unsigned long long C = S.chunk[ix];
   const unsigned int k = S.cnt[ix];
@@ -73,184 +92,290 @@ __device__ __forceinline__ void flush_chunk(LargeShared &S, unsigned int ix) {
   S.cnt[ix] = 0u;
 }
 
-// Add the NT terms a lane holds for this tile.  Every lane of the wave calls
-// this together; valid[j] masks lanes without a term j.  The LDS updates of
-// all NT terms are issued before any count is examined, so one wait covers
-// the tile; crossings of the threshold are rare and handled after a ballot.
-template <int NT>
-__device__ __forceinline__ void add_terms(LargeShared &S, const unsigned long long (&b)[NT], const bool (&valid)[NT],
-                                          int precombine, unsigned int tile, int lane, unsigned int thr) {
-  constexpr unsigned int kNone = 0xFFFFFFFFu;
-  unsigned int key[NT];
-  bool any_special = false;
-#pragma unroll
-  for (int j = 0; j < NT; j++) {
-    const bool sp = is_special(b[j]);
-    any_special |= valid[j] && sp;
-    key[j] = (valid[j] && !sp) ? (unsigned int)(b[j] >> 52) : kNone;
-  }
-  if (__builtin_expect(__ballot(any_special) != 0ull, 0)) {
-#pragma unroll
-    for (int j = 0; j < NT; j++)
-      if (valid[j] && is_special(b[j])) note_special(b[j], &S.spec[0], &S.spec[1], &S.spec[2]);
-  }
-  if (precombine > 0) {
-#pragma unroll
-    for (int j = 0; j < NT; j++) {
-      const unsigned int leader = __builtin_amdgcn_readfirstlane(key[j]);
-      const unsigned long long m = __ballot(key[j] == leader);
-      const int k = __popcll(m);
-      if (leader != kNone && k >= precombine) {
-        const unsigned long long s = wave_sum_u64(key[j] == leader ? b[j] : 0ull);
-        if (lane == __ffsll((long long)m) - 1) {
-          atomicAdd(&S.chunk[leader], s);
-          const unsigned int old = atomicAdd(&S.cnt[leader], (unsigned int)k);
-          if (old < thr && old + (unsigned int)k >= thr) mark_chunk(S, leader, tile);
-        }
-        if (key[j] == leader) key[j] = kNone;
-      }
-    }
-  }
-  unsigned int old[NT];
-#pragma unroll
-  for (int j = 0; j < NT; j++) {
-    old[j] = 0u;
-    if (key[j] != kNone) {
-      atomicAdd(&S.chunk[key[j]], b[j]);
-      old[j] = atomicAdd(&S.cnt[key[j]], 1u);
-    }
-  }
-  bool cross = false;
-#pragma unroll
-  for (int j = 0; j < NT; j++) cross |= (key[j] != kNone) && (old[j] == thr - 1u);
-  if (__builtin_expect(__ballot(cross) != 0ull, 0)) {
-#pragma unroll
-    for (int j = 0; j < NT; j++)
-      if (key[j] != kNone && old[j] == thr - 1u) mark_chunk(S, key[j], tile);
+// Carry mode: one wrap of chunk ix past 2^64 = 2^64 * 2^(e_eff-1075), which is
+// 2^(e_eff & 31) units of small chunk (e_eff >> 5) + 2, signed by the index.
+__device__ __forceinline__ void carry_out(LargeShared &S, unsigned int ix) {
+  const unsigned int e = ix & 2047u;
+  const unsigned int e_eff = e ? e : 1u;
+  const long long v = (long long)(1ull << (e_eff & 31u));
+  atomicAdd((unsigned long long *)&S.small[(e_eff >> 5) + 2], (unsigned long long)((ix >> 11) ? -v : v));
+}
+
+// Add `val` (k terms' worth) to chunk ix, with the mode's overflow rule.
+template <int MODE>
+__device__ __forceinline__ void chunk_add(LargeShared &S, unsigned int ix, unsigned long long val, unsigned int k,
+                                          unsigned int tile, unsigned int thr) {
+  if (MODE == kCountMode) {
+    atomicAdd(&S.chunk[ix], val);
+    const unsigned int old = atomicAdd(&S.cnt[ix], k);
+    if (old < thr && old + k >= thr) mark_chunk(S, ix, tile);
+  } else {
+    const unsigned long long old = atomicAdd(&S.chunk[ix], val);
+    if (old + val < old) carry_out(S, ix);
   }
 }
 
-// End of a tile: barrier, then transfer the chunks marked during the tile.
-// The "marked" flag is kept per tile mod 3 so one barrier per tile suffices:
-// flag[t%3] is set during tile t, read after tile t's barrier, and cleared
-// during tile t+2.
+// The value a term contributes to its chunk in each mode.
+template <int MODE>
+__device__ __forceinline__ unsigned long long chunk_value(unsigned long long b) {
+  return MODE == kCountMode ? b : mantissa53(b);
+}
+
+// Add one term per lane (the general, rarely used path).  Every lane of the
+// wave calls this together; `valid` masks lanes without a term.  Handles
+// infinities and NaNs (side words), the cross-wave pre-combine of a widely
+// shared chunk, and the mode's overflow rule.
+template <int MODE>
+__device__ __forceinline__ void add_slot(LargeShared &S, unsigned long long b, bool valid, int precombine,
+                                         unsigned int tile, int lane, unsigned int thr) {
+  constexpr unsigned int kNone = 0xFFFFFFFFu;
+  const bool sp = valid && is_special(b);
+  if (sp) note_special(b, &S.spec[0], &S.spec[1], &S.spec[2]);
+  unsigned int key = (valid && !sp) ? (unsigned int)(b >> 52) : kNone;
+  const unsigned long long val = chunk_value<MODE>(b);
+  if (precombine > 0) {
+    const unsigned int ld = __builtin_amdgcn_readfirstlane(key);
+    const unsigned long long m = __ballot(key == ld);
+    const int k = __popcll(m);
+    if (ld != kNone && k >= precombine) {
+      // count mode: k raw patterns sum exactly mod 2^64 (the count corrects);
+      // carry mode: k < 2^11 mantissas below 2^53 sum below 2^64
+      const unsigned long long s = wave_sum_u64(key == ld ? val : 0ull);
+      if (lane == __ffsll((long long)m) - 1) chunk_add<MODE>(S, ld, s, (unsigned int)k, tile, thr);
+      if (key == ld) key = kNone;
+    }
+  }
+  if (key != kNone) chunk_add<MODE>(S, key, val, 1u, tile, thr);
+}
+
+// Slow tile: re-read this lane's terms (16-byte vectors tb + j*stride for
+// j < nslots, present below `limit`) and add them one slot at a time.  Kept
+// out of line so the hot loop stays small.
+template <int MODE>
+__device__ __noinline__ void slow_tile(LargeShared *S, const ulonglong2 *__restrict__ xv, long long tb,
+                                       long long limit, int stride, int nslots, int precombine, unsigned int tile,
+                                       unsigned int thr) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll 1
+  for (int j = 0; j < nslots; j++) {
+    const long long idx = tb + (long long)j * stride;
+    const bool ok = idx < limit;
+    ulonglong2 v = make_ulonglong2(0ull, 0ull);
+    if (ok) v = xv[idx];
+    add_slot<MODE>(*S, v.x, ok, precombine, tile, lane, thr);
+    add_slot<MODE>(*S, v.y, ok, precombine, tile, lane, thr);
+  }
+}
+
+// Fast tile: the NT terms every lane holds are all present.  Returns false,
+// having changed nothing, when the tile needs the slow path (an infinity or
+// NaN somewhere, or a chunk shared by many lanes but not by the whole tile).
+//   * whole wave, whole tile in one chunk: each lane sums its NT values, the
+//     wave sums those, one lane adds the total (64*NT terms) to the chunk;
+//   * otherwise one 64-bit LDS add per term (plus a count add in count
+//     mode), all issued before any returned value is examined; the rare
+//     threshold crossings or carries are found with one ballot per term.
+template <int NT, int MODE>
+__device__ __forceinline__ bool fast_tile(LargeShared &S, const unsigned long long (&b)[NT], int precombine,
+                                          unsigned int tile, int lane, unsigned int thr) {
+  static_assert(MODE == kCountMode || 64 * NT < 2048, "carry mode: a wave's tile sum must stay below 2^64");
+  unsigned long long odd = 0;
+  unsigned int key[NT];
+#pragma unroll
+  for (int j = 0; j < NT; j++) {
+    odd |= __ballot(!__builtin_isfinite(__longlong_as_double((long long)b[j])));
+    key[j] = (unsigned int)(b[j] >> 52);
+  }
+  if (odd) return false;
+  if (precombine > 0) {
+    const unsigned int leader = __builtin_amdgcn_readfirstlane(key[0]);
+    unsigned long long all = ~0ull;
+#pragma unroll
+    for (int j = 0; j < NT; j++) all &= __ballot(key[j] == leader);
+    if (all == ~0ull) {
+      unsigned long long s = 0;
+#pragma unroll
+      for (int j = 0; j < NT; j++) s += chunk_value<MODE>(b[j]);
+      s = wave_sum_u64(s);
+      if (lane == 0) chunk_add<MODE>(S, leader, s, 64u * NT, tile, thr);
+      return true;
+    }
+    if (__popcll(__ballot(key[0] == leader)) >= precombine) return false;
+  }
+  if (MODE == kCountMode) {
+    unsigned int old[NT];
+#pragma unroll
+    for (int j = 0; j < NT; j++) {
+      atomicAdd(&S.chunk[key[j]], b[j]);
+      old[j] = atomicAdd(&S.cnt[key[j]], 1u);
+    }
+    unsigned long long cross = 0;
+#pragma unroll
+    for (int j = 0; j < NT; j++) cross |= __ballot(old[j] == thr - 1u);
+    if (cross) {
+#pragma unroll
+      for (int j = 0; j < NT; j++)
+        if (old[j] == thr - 1u) mark_chunk(S, key[j], tile);
+    }
+  } else {
+    unsigned long long m[NT], old[NT];
+#pragma unroll
+    for (int j = 0; j < NT; j++) {
+      m[j] = mantissa53(b[j]);
+      old[j] = atomicAdd(&S.chunk[key[j]], m[j]);
+    }
+    unsigned long long wrap = 0;
+#pragma unroll
+    for (int j = 0; j < NT; j++) wrap |= __ballot(old[j] + m[j] < old[j]);
+    if (wrap) {
+#pragma unroll
+      for (int j = 0; j < NT; j++)
+        if (old[j] + m[j] < old[j]) carry_out(S, key[j]);
+    }
+  }
+  return true;
+}
+
+// Count mode: transfer the chunks marked during a tile (out of line: rare).
+__device__ __noinline__ void flush_marked(LargeShared *S) {
+  const int tid = threadIdx.x;
+  if (tid < kLChunks / 32) {
+    unsigned int bits = S->flushbits[tid];
+    if (bits) {
+      S->flushbits[tid] = 0u;
+      while (bits) {
+        const int bp = __ffs(bits) - 1;
+        bits &= bits - 1u;
+        flush_chunk(*S, (unsigned int)(tid * 32 + bp));
+      }
+    }
+  }
+}
+
+// Count mode, end of a tile: barrier, then transfer the chunks marked during
+// the tile.  The "marked" flag is kept per tile mod 3 so one barrier per tile
+// suffices: flag[t%3] is set during tile t, read after tile t's barrier, and
+// cleared during tile t+2.  Carry mode needs nothing here.
+template <int MODE>
 __device__ __forceinline__ void tile_end(LargeShared &S, unsigned int tile, int tid) {
+  if (MODE != kCountMode) return;
   lds_barrier();
   const unsigned int f = S.flag[tile % 3];
   if (tid == 0) S.flag[(tile + 2) % 3] = 0u;
   if (f) {
-    if (tid < kLChunks / 32) {
-      unsigned int bits = S.flushbits[tid];
-      if (bits) {
-        S.flushbits[tid] = 0u;
-        while (bits) {
-          const int bp = __ffs(bits) - 1;
-          bits &= bits - 1u;
-          flush_chunk(S, (unsigned int)(tid * 32 + bp));
-        }
-      }
-    }
+    flush_marked(&S);
     lds_barrier();
   }
 }
 
+// 16-byte streaming load that does not displace cached data (the input is
+// read exactly once).
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ ulonglong2 stream_load(const ulonglong2 *p) {
+  const u64x2 v = __builtin_nontemporal_load(reinterpret_cast<const u64x2 *>(p));
+  return make_ulonglong2(v.x, v.y);
+}
+
 // Add x[r0 .. r1) into the workgroup's large accumulator.  A misaligned first
-// term and an odd last term are added as scalars; the rest by 16-byte loads,
-// BLOCK*VEC per tile, with the next two tiles' loads in flight.
-template <int BLOCK, int VEC>
+// term and an odd last term are added as scalars.  The 16-byte vectors are
+// split into one contiguous stream per wavefront; a wave's tile is 64*VEC
+// vectors (each load instruction covers 1 KiB), with the next DEPTH tiles'
+// loads in flight in a ring of register buffers.  Every wave runs the same
+// number of full tiles (count mode puts a workgroup barrier after each); the
+// leftover vectors of each stream form one last, partial tile.
+template <int BLOCK, int VEC, int DEPTH, int MODE>
 __device__ __forceinline__ void accumulate_range(LargeShared &S, const double *__restrict__ x, long long r0,
                                                  long long r1, int precombine, unsigned int &tile) {
-  constexpr int TILE_V = BLOCK * VEC;
-  constexpr unsigned int THR = kCap - 2 * TILE_V;
-  static_assert(2 * TILE_V < kCap, "tile too large for the count bound");
-  const int tid = threadIdx.x, lane = tid & 63;
+  constexpr int NW = BLOCK / 64;
+  constexpr int TILE_W = 64 * VEC;            // vectors per wave per tile
+  constexpr int TILE_V = BLOCK * VEC;         // vectors per workgroup per tile
+  static_assert(MODE != kCountMode || 2 * TILE_V < kCap, "tile too large for the count bound");
+  constexpr unsigned int THR = (MODE == kCountMode) ? (unsigned int)(kCap - 2 * TILE_V) : 0u;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (r1 <= r0) return;
   const long long head = (reinterpret_cast<uintptr_t>(x + r0) & 15) ? 1 : 0;
   const long long a = r0 + head;
   const long long nv = (r1 - a) >> 1;
   const bool has_tail = ((r1 - a) & 1) != 0;
   if (head || has_tail) {
-    unsigned long long b[1] = {0ull};
-    bool valid[1] = {false};
-    if (tid == 0 && head) { b[0] = as_bits(x[r0]); valid[0] = true; }
-    if (tid == 1 && has_tail) { b[0] = as_bits(x[r1 - 1]); valid[0] = true; }
-    add_terms<1>(S, b, valid, precombine, tile, lane, THR);
-    tile_end(S, tile++, tid);
+    unsigned long long b = 0ull;
+    bool valid = false;
+    if (tid == 0 && head) { b = as_bits(x[r0]); valid = true; }
+    if (tid == 1 && has_tail) { b = as_bits(x[r1 - 1]); valid = true; }
+    add_slot<MODE>(S, b, valid, precombine, tile, lane, THR);
+    tile_end<MODE>(S, tile++, tid);
   }
   const ulonglong2 *__restrict__ xv = reinterpret_cast<const ulonglong2 *>(x + a);
-  const long long ntiles = nv / TILE_V;
-  // Two tiles in flight: buffer A holds even tiles, B odd ones.  Loads are
-  // unconditional (an index past the last tile re-reads the last tile) so the
-  // compiler's wait counts stay exact and a prefetch is never waited early.
-  ulonglong2 bufA[VEC], bufB[VEC];
-  auto load = [&](ulonglong2(&buf)[VEC], long long t) {
-    const long long tb = (t < ntiles ? t : ntiles - 1) * TILE_V + tid;
+  const long long q = nv / NW;                       // vectors per stream (the last takes the rest)
+  const long long ws = (long long)wave * q;
+  const long long we = (wave == NW - 1) ? nv : ws + q;
+  const long long ntiles = q / TILE_W;               // full tiles, the same for every wave
+  // Loads are unconditional (an index past the last tile re-reads the last
+  // tile) so the compiler's wait counts stay exact and a prefetch is never
+  // waited for early.
+  ulonglong2 buf[DEPTH][VEC];
+  auto load = [&](ulonglong2(&bf)[VEC], long long t) {
+    const long long tb = ws + (t < ntiles ? t : ntiles - 1) * TILE_W + lane;
 #pragma unroll
-    for (int j = 0; j < VEC; j++) buf[j] = xv[tb + j * BLOCK];
-    // keep the scheduler from hoisting work on the other buffer above these
+    for (int j = 0; j < VEC; j++) bf[j] = stream_load(&xv[tb + j * 64]);
+    // keep the scheduler from hoisting work on other buffers above these
     // loads (which would force an early wait on them)
     __builtin_amdgcn_sched_barrier(0);
   };
-  auto process = [&](const ulonglong2(&buf)[VEC]) {
+  auto process = [&](const ulonglong2(&bf)[VEC], long long t) {
     unsigned long long b[2 * VEC];
-    bool valid[2 * VEC];
 #pragma unroll
     for (int j = 0; j < VEC; j++) {
-      b[2 * j] = buf[j].x;
-      b[2 * j + 1] = buf[j].y;
-      valid[2 * j] = valid[2 * j + 1] = true;
+      b[2 * j] = bf[j].x;
+      b[2 * j + 1] = bf[j].y;
     }
-    add_terms<2 * VEC>(S, b, valid, precombine, tile, lane, THR);
-    tile_end(S, tile++, tid);
+    if (!fast_tile<2 * VEC, MODE>(S, b, precombine, tile, lane, THR))
+      slow_tile<MODE>(&S, xv, ws + t * TILE_W + lane, we, 64, VEC, precombine, tile, THR);
+    tile_end<MODE>(S, tile++, tid);
   };
   if (ntiles > 0) {
-    load(bufA, 0);
-    load(bufB, 1);
-    for (long long t = 0; t < ntiles; t += 2) {
-      process(bufA);
-      load(bufA, t + 2);
-      if (t + 1 < ntiles) process(bufB);
-      load(bufB, t + 3);
+#pragma unroll
+    for (int d = 0; d < DEPTH; d++) load(buf[d], d);
+    for (long long t = 0; t < ntiles; t += DEPTH) {
+#pragma unroll
+      for (int d = 0; d < DEPTH; d++) {
+        if (d == 0 || t + d < ntiles) process(buf[d], t + d);
+        load(buf[d], t + d + DEPTH);
+      }
     }
   }
-  const long long base = ntiles * TILE_V;
-  if (base < nv) {
-    unsigned long long b[2 * VEC];
-    bool valid[2 * VEC];
-#pragma unroll
-    for (int j = 0; j < VEC; j++) {
-      const long long idx = base + j * BLOCK + tid;
-      const bool ok = idx < nv;
-      ulonglong2 v = make_ulonglong2(0ull, 0ull);
-      if (ok) v = xv[idx];
-      b[2 * j] = v.x;
-      b[2 * j + 1] = v.y;
-      valid[2 * j] = valid[2 * j + 1] = ok;
-    }
-    add_terms<2 * VEC>(S, b, valid, precombine, tile, lane, THR);
-    tile_end(S, tile++, tid);
+  // leftover: fewer than TILE_W vectors per stream (plus up to NW-1 more in
+  // the last), so at most VEC+1 slots and fewer terms than one full tile
+  if (nv > (long long)NW * ntiles * TILE_W) {
+    slow_tile<MODE>(&S, xv, ws + ntiles * TILE_W + lane, we, 64, VEC + 1, precombine, tile, THR);
+    tile_end<MODE>(S, tile++, tid);
   }
 }
 
 // Transfer every used chunk into S.small.  Group gi holds the 64 chunks whose
 // exponent field has top six bits gi (both signs, 32 low-exponent values);
 // all of them land on small chunks gi .. gi+2, so three wavefront sums and
-// three LDS adds serve the group.  With `clean`, the chunks and counts read
-// are reset to zero (so the next unit of work needs no initialisation).
-template <int BLOCK, bool clean>
+// three LDS adds serve the group.  With `clean`, the chunks (and counts) read
+// are reset to zero, so the next unit of work needs no initialisation.
+template <int BLOCK, bool clean, int MODE>
 __device__ __forceinline__ void final_flush(LargeShared &S) {
   constexpr int NW = BLOCK / 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   __syncthreads();
   for (int gi = wave; gi < 64; gi += NW) {
     const unsigned int ix = ((unsigned int)(lane >> 5) << 11) | (unsigned int)(gi * 32 + (lane & 31));
-    const unsigned int k = S.cnt[ix];
+    const unsigned long long C = S.chunk[ix];
+    const unsigned int k = (MODE == kCountMode) ? S.cnt[ix] : (C != 0ull ? 1u : 0u);
     if (__ballot(k != 0u) == 0ull) continue;
     long long p0 = 0, p1 = 0, p2 = 0;
     int h = gi;
     if (k) {
-      chunk_pieces(ix, S.chunk[ix], k, p0, p1, p2, h);
-      if (clean) { S.chunk[ix] = 0ull; S.cnt[ix] = 0u; }
+      if (MODE == kCountMode) chunk_pieces(ix, C, k, p0, p1, p2, h);
+      else mantissa_sum_pieces(ix, C, p0, p1, p2, h);
+      if (clean) {
+        S.chunk[ix] = 0ull;
+        if (MODE == kCountMode) S.cnt[ix] = 0u;
+      }
     }
     p0 = wave_sum_i64(p0);
     p1 = wave_sum_i64(p1);
@@ -304,6 +429,100 @@ __device__ __forceinline__ bool merge_and_round(long long *s_small, unsigned lon
   if (tid == 97) spec[1] = atomicExch(&g->neg_inf, 0ull);
   if (tid == 98) spec[2] = atomicExch(&g->nan_bits, 0ull);
   if (tid == 99) atomicExch(&g->ticket, 0u);
+  __syncthreads();
+  if (tid == 0) out[0] = __longlong_as_double((long long)round_chunks(s_small, spec[0], spec[1], spec[2], s_D));
+  __syncthreads();
+  return true;
+}
+
+// Merge by rows (used by the one-sum kernels, where every workgroup of the
+// grid takes part).  Everything one workgroup hands to another goes through
+// device-coherent accesses (agent-scope atomic loads and stores, which the
+// hardware performs at the device's coherence point rather than in a
+// per-die cache), and each producer waits for its stores to complete before
+// it takes a ticket.  That orders the hand-over without device-wide cache
+// write-back or invalidation, which cost several microseconds each here.
+// Returns true in the workgroup that wrote *out.  Called by every thread
+// (block of at least 128 threads).
+__device__ __forceinline__ void coherent_store(long long *p, long long v) {
+  __hip_atomic_store((unsigned long long *)p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ long long coherent_load(const long long *p) {
+  return (long long)__hip_atomic_load((const unsigned long long *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Wait until this thread's memory operations have completed.
+__device__ __forceinline__ void wait_memory() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+__device__ __forceinline__ unsigned int ticket_add(unsigned int *p) {
+  return __hip_atomic_fetch_add(p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Combine word w of rows [r0, r0+nr) of a row array: chunk words add, the
+// infinity flags OR, the NaN word takes the unsigned maximum.  Sixteen loads
+// are in flight at a time.
+template <int KIND>
+__device__ __forceinline__ long long combine_rows_kind(const long long (*rows)[kRowWords], unsigned int r0,
+                                                       unsigned int nr, int w) {
+  long long acc = 0;
+  for (unsigned int base = 0; base < nr; base += 16) {
+    long long v[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) v[k] = (base + k < nr) ? coherent_load(&rows[r0 + base + k][w]) : 0;
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+      if (KIND == 0) acc += v[k];
+      else if (KIND == 1) acc |= v[k];
+      else acc = ((unsigned long long)v[k] > (unsigned long long)acc) ? v[k] : acc;
+    }
+  }
+  return acc;
+}
+
+__device__ __forceinline__ long long combine_rows(const long long (*rows)[kRowWords], unsigned int r0,
+                                                  unsigned int nr, int w) {
+  if (w < 68) return combine_rows_kind<0>(rows, r0, nr, w);
+  if (w < 70) return combine_rows_kind<1>(rows, r0, nr, w);
+  return combine_rows_kind<2>(rows, r0, nr, w);
+}
+
+__device__ __forceinline__ bool merge_rows_and_round(long long *s_small, unsigned long long *spec,
+                                                     unsigned int *s_flag, unsigned int *s_D,
+                                                     MergeRows *__restrict__ M, double *__restrict__ out) {
+  const int tid = threadIdx.x;
+  const unsigned int G = gridDim.x, b = blockIdx.x;
+  __syncthreads();
+  if (G == 1) {
+    if (tid == 0) out[0] = __longlong_as_double((long long)round_chunks(s_small, spec[0], spec[1], spec[2], s_D));
+    __syncthreads();
+    return true;
+  }
+  if (tid < 68) coherent_store(&M->rows[b][tid], (tid < kSChunks) ? s_small[tid] : 0);
+  else if (tid < 71) coherent_store(&M->rows[b][tid], (long long)spec[tid - 68]);
+  wait_memory();
+  __syncthreads();
+  const unsigned int grp = b / kMergeGroup;
+  const unsigned int g0 = grp * kMergeGroup;
+  const unsigned int gsz = (G - g0 < (unsigned int)kMergeGroup) ? G - g0 : (unsigned int)kMergeGroup;
+  const unsigned int ngrp = (G + kMergeGroup - 1) / kMergeGroup;
+  if (tid == 0) s_flag[0] = (ticket_add(&M->gticket[grp]) == gsz - 1u) ? 1u : 0u;
+  __syncthreads();
+  if (!s_flag[0]) return false;
+  if (tid < 71) coherent_store(&M->grows[grp][tid], combine_rows(M->rows, g0, gsz, tid));
+  if (tid == 0) __hip_atomic_store(&M->gticket[grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  wait_memory();
+  __syncthreads();
+  if (tid == 0) s_flag[1] = (ticket_add(&M->ticket) == ngrp - 1u) ? 1u : 0u;
+  __syncthreads();
+  if (!s_flag[1]) return false;
+  if (tid < 71) {
+    const long long acc = combine_rows(M->grows, 0, ngrp, tid);
+    if (tid < 68) s_small[tid] = acc;
+    else spec[tid - 68] = (unsigned long long)acc;
+  }
+  if (tid == 0) __hip_atomic_store(&M->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
   if (tid == 0) out[0] = __longlong_as_double((long long)round_chunks(s_small, spec[0], spec[1], spec[2], s_D));
   __syncthreads();

@@ -21,6 +21,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "exsum_internal.h"
+
 namespace exsum {
 
 constexpr int kSChunks = 67;          // small accumulator chunks
@@ -40,6 +42,22 @@ struct alignas(64) GlobalAcc {
 };
 static_assert(sizeof(GlobalAcc) == 576, "GlobalAcc layout");
 
+// Merge workspace of one multi-workgroup sum.  Each workgroup writes its
+// small accumulator as a row with plain stores; groups of kMergeGroup
+// workgroups are summed by the group's last arrival, and the group sums by
+// the last group to finish.  Only two small counters are atomic, so no
+// address sees more than max(kMergeGroup, groups) atomic updates.  Row
+// layout: words 0..66 chunks, 68 +Inf seen, 69 -Inf seen, 70 max NaN bits.
+constexpr int kMergeGroup = 16;
+constexpr int kRowWords = 72;
+struct MergeRows {
+  long long rows[kMaxGrid][kRowWords];
+  long long grows[kMaxGrid / kMergeGroup][kRowWords];
+  unsigned int gticket[kMaxGrid / kMergeGroup];
+  unsigned int ticket;
+  unsigned int pad[63];
+};
+
 // ---- synchronisation -------------------------------------------------------
 
 // Workgroup barrier that waits only for this wave's LDS traffic.  Global loads
@@ -50,15 +68,30 @@ __device__ __forceinline__ void lds_barrier() {
 
 // ---- wavefront reductions (all 64 lanes active) ----------------------------
 
+// Move a 64-bit value across lanes with a DPP pattern (two 32-bit moves).
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_mov_u64(unsigned long long v) {
+  const unsigned int lo = (unsigned int)__builtin_amdgcn_mov_dpp((int)(unsigned int)v, CTRL, 0xF, 0xF, false);
+  const unsigned int hi = (unsigned int)__builtin_amdgcn_mov_dpp((int)(unsigned int)(v >> 32), CTRL, 0xF, 0xF, false);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v, int lane) {
+  const unsigned int lo = (unsigned int)__builtin_amdgcn_readlane((int)(unsigned int)v, lane);
+  const unsigned int hi = (unsigned int)__builtin_amdgcn_readlane((int)(unsigned int)(v >> 32), lane);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Sum over the 64 lanes (mod 2^64), returned as a wave-uniform value.
+// Within each row of 16 lanes: swap neighbours, swap pairs, mirror the
+// half-rows, mirror the row (every lane then holds its row sum); the four
+// row sums are then read out and added.
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    unsigned int lo = (unsigned int)v, hi = (unsigned int)(v >> 32);
-    unsigned int olo = __shfl_xor(lo, d, 64);
-    unsigned int ohi = __shfl_xor(hi, d, 64);
-    v += ((unsigned long long)ohi << 32) | olo;
-  }
-  return v;
+  v += dpp_mov_u64<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_mov_u64<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_mov_u64<0x141>(v);   // row_half_mirror
+  v += dpp_mov_u64<0x140>(v);   // row_mirror
+  return readlane_u64(v, 0) + readlane_u64(v, 16) + readlane_u64(v, 32) + readlane_u64(v, 48);
 }
 
 __device__ __forceinline__ long long wave_sum_i64(long long v) {
@@ -86,6 +119,25 @@ __device__ __forceinline__ void chunk_pieces(unsigned int ix, unsigned long long
   long long b = (long long)(low64 >> 32);
   long long c = (long long)top;
   const long long neg = -(long long)(ix >> 11);      // 0 or -1
+  p0 = (a ^ neg) - neg;
+  p1 = (b ^ neg) - neg;
+  p2 = (c ^ neg) - neg;
+}
+
+// A chunk holding the plain sum T (< 2^64) of the 53-bit mantissas of terms
+// with index ix: three signed pieces for small chunks hi .. hi+2.
+__device__ __forceinline__ void mantissa_sum_pieces(unsigned int ix, unsigned long long T, long long &p0,
+                                                    long long &p1, long long &p2, int &hi) {
+  const unsigned int e = ix & 2047u;
+  const unsigned int e_eff = e ? e : 1u;
+  const unsigned int lo = e_eff & 31u;
+  hi = (int)(e_eff >> 5);
+  const unsigned long long low64 = T << lo;
+  const unsigned long long top = lo ? (T >> (64 - lo)) : 0ull;
+  const long long a = (long long)(low64 & 0xFFFFFFFFull);
+  const long long b = (long long)(low64 >> 32);
+  const long long c = (long long)top;
+  const long long neg = -(long long)(ix >> 11);
   p0 = (a ^ neg) - neg;
   p1 = (b ^ neg) - neg;
   p2 = (c ^ neg) - neg;

@@ -6,12 +6,15 @@
 
 namespace exsum {
 
+constexpr int kMaxGrid = 8192;       // most workgroups one single-sum launch may use
+
 struct GlobalAcc;
+struct MergeRows;
 
 // Per-(device, stream) workspace.  Everything the kernels write here is left
 // zeroed when a call completes.
 struct Workspace {
-  GlobalAcc *acc = nullptr;            // merge target of the single-sum kernels
+  MergeRows *rows = nullptr;           // merge workspace of the single-sum kernels
   double *partials = nullptr;          // per-workgroup partials of the inexact sum
   unsigned int *ticket = nullptr;      // ticket of the inexact sum
   int max_grid = 0;                    // capacity of `partials`
@@ -22,9 +25,10 @@ struct Workspace {
 };
 
 // Launchers (kernels_sum.hip).  Return a hipError_t.
-hipError_t launch_large(const double *x, int64_t n, GlobalAcc *g, double *out, hipStream_t s,
-                        int block, int vec, int grid, int precombine);
-hipError_t launch_small(const double *x, int64_t n, GlobalAcc *g, double *out, hipStream_t s,
+hipError_t launch_large(const double *x, int64_t n, MergeRows *M, double *out, hipStream_t s,
+                        int block, int vec, int depth, int mode, int grid, int precombine);
+bool large_variant_exists(int block, int vec, int depth, int mode);
+hipError_t launch_small(const double *x, int64_t n, MergeRows *M, double *out, hipStream_t s,
                         int grid);
 hipError_t launch_inexact(const double *x, int64_t n, double *partials, unsigned int *ticket,
                           double *out, hipStream_t s, int grid);
@@ -35,6 +39,6 @@ hipError_t launch_segmented(const double *x, const int64_t *offsets, int64_t nse
                             void *ws, int64_t cap, hipStream_t s, int grid, int64_t small_max,
                             int64_t tile, int precombine);
 
-constexpr size_t kGlobalAccBytes = 1024;
+size_t merge_rows_bytes();
 
 }  // namespace exsum

@@ -134,8 +134,8 @@ __global__ __launch_bounds__(BLOCK) void seg_kernel(const double *__restrict__ x
     const long long start = offsets[e.seg], end = offsets[e.seg + 1];
     const long long r0 = start + (long long)t * tile_terms;
     const long long r1 = (r0 + tile_terms < end) ? r0 + tile_terms : end;
-    accumulate_range<BLOCK, VEC>(S, x, r0, r1, precombine, tile);
-    final_flush<BLOCK, true>(S);
+    accumulate_range<BLOCK, VEC, 2, kCountMode>(S, x, r0, r1, precombine, tile);
+    final_flush<BLOCK, true, kCountMode>(S);
     merge_and_round(S.small, S.spec, &S.ticket, S.D, &Lw.accs[eidx], e.ntiles, &out[e.seg]);
     if (tid < 68) S.small[tid] = 0;
     if (tid < 3) S.spec[tid] = 0ull;

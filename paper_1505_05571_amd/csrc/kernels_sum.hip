@@ -3,19 +3,21 @@
 //
 // Large kernel: workgroup b owns terms [n*b/G, n*(b+1)/G) and a private large
 // superaccumulator in LDS; it transfers every used chunk into its small
-// superaccumulator, adds that into the call's global accumulator with
-// integer atomics, and the last workgroup to finish rounds once
-// (Discussion: split the array, sum the parts exactly, add the small
-// superaccumulators, round the total).
+// superaccumulator and publishes that as a row; rows are added with integer
+// arithmetic in two levels (groups of workgroups, then groups) and the last
+// finisher rounds once (Discussion: split the array, sum the parts exactly,
+// add the small superaccumulators, round the total).  One workgroup per
+// compute unit is the intended grid: each holds the whole LDS budget it needs
+// and is never starved by a younger workgroup on the same unit.
 #include "exsum_blocks.h"
 #include "exsum_internal.h"
 
 namespace exsum {
 namespace {
 
-template <int BLOCK, int VEC>
+template <int BLOCK, int VEC, int DEPTH, int MODE>
 __global__ __launch_bounds__(BLOCK) void large_kernel(const double *__restrict__ x, long long n,
-                                                      GlobalAcc *__restrict__ g, double *__restrict__ out,
+                                                      MergeRows *__restrict__ M, double *__restrict__ out,
                                                       int precombine) {
   __shared__ LargeShared S;
   const int tid = threadIdx.x;
@@ -25,9 +27,9 @@ __global__ __launch_bounds__(BLOCK) void large_kernel(const double *__restrict__
   const long long r0 = n * (long long)blockIdx.x / G;
   const long long r1 = n * (long long)(blockIdx.x + 1) / G;
   unsigned int tile = 0;
-  accumulate_range<BLOCK, VEC>(S, x, r0, r1, precombine, tile);
-  final_flush<BLOCK, false>(S);
-  merge_and_round(S.small, S.spec, &S.ticket, S.D, g, gridDim.x, out);
+  accumulate_range<BLOCK, VEC, DEPTH, MODE>(S, x, r0, r1, precombine, tile);
+  final_flush<BLOCK, false, MODE>(S);
+  merge_rows_and_round(S.small, S.spec, S.bcast, S.D, M, out);
 }
 
 // Small-only kernel: every wavefront sums a contiguous part into its own
@@ -35,12 +37,12 @@ __global__ __launch_bounds__(BLOCK) void large_kernel(const double *__restrict__
 // (each below 2^33 per chunk after the final carry step) and merges.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void small_kernel(const double *__restrict__ x, long long n,
-                                                      GlobalAcc *__restrict__ g, double *__restrict__ out) {
+                                                      MergeRows *__restrict__ M, double *__restrict__ out) {
   constexpr int NW = BLOCK / 64;
   __shared__ long long s_acc[NW][68];
   __shared__ long long s_tot[68];
   __shared__ unsigned long long s_spec[3];
-  __shared__ unsigned int s_ticket;
+  __shared__ unsigned int s_flag[2];
   __shared__ unsigned int s_D[70];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int i = tid; i < NW * 68; i += BLOCK) (&s_acc[0][0])[i] = 0;
@@ -58,7 +60,7 @@ __global__ __launch_bounds__(BLOCK) void small_kernel(const double *__restrict__
     for (int w = 0; w < NW; w++) t += s_acc[w][tid];
     s_tot[tid] = t;
   }
-  merge_and_round(s_tot, s_spec, &s_ticket, s_D, g, gridDim.x, out);
+  merge_rows_and_round(s_tot, s_spec, s_flag, s_D, M, out);
 }
 
 // Inexact comparator: ordinary binary64 additions per thread (2*VEC
@@ -132,27 +134,45 @@ __global__ __launch_bounds__(BLOCK) void inexact_kernel(const double *__restrict
 
 }  // namespace
 
-hipError_t launch_large(const double *x, int64_t n, GlobalAcc *g, double *out, hipStream_t s, int block,
-                        int vec, int grid, int precombine) {
+// Built variants (block, vec, depth, mode).  Count mode needs
+// 2*block*vec < 4096 (the count bound per tile); carry mode does not.
+#define EXSUM_LARGE_VARIANTS(X) \
+  X(256, 6, 3, kCountMode)      \
+  X(256, 4, 3, kCountMode)      \
+  X(256, 2, 4, kCountMode)      \
+  X(512, 3, 2, kCountMode)      \
+  X(512, 2, 2, kCountMode)      \
+  X(256, 4, 3, kCarryMode)      \
+  X(512, 4, 2, kCarryMode)      \
+  X(512, 2, 4, kCarryMode)      \
+  X(1024, 2, 2, kCarryMode)     \
+  X(1024, 4, 2, kCarryMode)
+
+hipError_t launch_large(const double *x, int64_t n, MergeRows *M, double *out, hipStream_t s, int block,
+                        int vec, int depth, int mode, int grid, int precombine) {
   if (grid < 1) grid = 1;
-#define EXSUM_LARGE_CASE(B, V)                                                                   \
-  if (block == B && vec == V) {                                                                  \
-    hipLaunchKernelGGL((large_kernel<B, V>), dim3(grid), dim3(B), 0, s, x, (long long)n, g, out, \
-                       precombine);                                                              \
-    return hipGetLastError();                                                                    \
+#define EXSUM_LAUNCH(B, V, D, MD)                                                                       \
+  if (block == B && vec == V && depth == D && mode == MD) {                                             \
+    hipLaunchKernelGGL((large_kernel<B, V, D, MD>), dim3(grid), dim3(B), 0, s, x, (long long)n, M, out, \
+                       precombine);                                                                     \
+    return hipGetLastError();                                                                           \
   }
-  EXSUM_LARGE_CASE(256, 2)
-  EXSUM_LARGE_CASE(256, 4)
-  EXSUM_LARGE_CASE(256, 6)
-  EXSUM_LARGE_CASE(512, 2)
-  EXSUM_LARGE_CASE(512, 3)
-#undef EXSUM_LARGE_CASE
+  EXSUM_LARGE_VARIANTS(EXSUM_LAUNCH)
+#undef EXSUM_LAUNCH
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_small(const double *x, int64_t n, GlobalAcc *g, double *out, hipStream_t s, int grid) {
+bool large_variant_exists(int block, int vec, int depth, int mode) {
+#define EXSUM_EXISTS(B, V, D, MD) \
+  if (block == B && vec == V && depth == D && mode == MD) return true;
+  EXSUM_LARGE_VARIANTS(EXSUM_EXISTS)
+#undef EXSUM_EXISTS
+  return false;
+}
+
+hipError_t launch_small(const double *x, int64_t n, MergeRows *M, double *out, hipStream_t s, int grid) {
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL((small_kernel<256>), dim3(grid), dim3(256), 0, s, x, (long long)n, g, out);
+  hipLaunchKernelGGL((small_kernel<256>), dim3(grid), dim3(256), 0, s, x, (long long)n, M, out);
   return hipGetLastError();
 }
 
@@ -164,4 +184,8 @@ hipError_t launch_inexact(const double *x, int64_t n, double *partials, unsigned
   return hipGetLastError();
 }
 
+}  // namespace exsum
+
+namespace exsum {
+size_t merge_rows_bytes() { return sizeof(MergeRows); }
 }  // namespace exsum

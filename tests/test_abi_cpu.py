@@ -64,10 +64,13 @@ def test_config_roundtrip_and_validation(lib):
     c0 = ex.exsum_get_config()
     try:
         c = ex.exsum_get_config()
-        c.large_block, c.large_vec = 512, 3
+        c.large_block, c.large_vec, c.large_depth, c.large_mode = 512, 3, 2, 0
         ex.exsum_set_config(c)
         assert ex.exsum_get_config().large_vec == 3
-        for field, bad in [("large_vec", 8), ("large_block", 128), ("precombine", -1),
+        c.large_block, c.large_vec, c.large_depth, c.large_mode = 1024, 4, 2, 1
+        ex.exsum_set_config(c)
+        assert ex.exsum_get_config().large_mode == 1
+        for field, bad in [("large_vec", 8), ("large_block", 128), ("precombine", -1), ("large_mode", 2),
                            ("seg_tile", 1000), ("seg_small_max", 1 << 20), ("large_grid", -3)]:
             c = ex.exsum_get_config()
             setattr(c, field, bad)

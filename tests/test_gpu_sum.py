@@ -46,11 +46,14 @@ def cfg_with(ex, **kw):
 
 
 LARGE_VARIANTS = [
-    dict(large_block=256, large_vec=4, precombine=16),
-    dict(large_block=256, large_vec=2, precombine=0),
-    dict(large_block=256, large_vec=6, precombine=1),
-    dict(large_block=512, large_vec=2, precombine=32),
-    dict(large_block=512, large_vec=3, precombine=8),
+    dict(large_block=256, large_vec=6, large_depth=3, large_mode=0, precombine=16),
+    dict(large_block=256, large_vec=4, large_depth=3, large_mode=1, precombine=16),
+    dict(large_block=256, large_vec=2, large_depth=4, large_mode=0, precombine=0),
+    dict(large_block=1024, large_vec=4, large_depth=2, large_mode=1, precombine=0),
+    dict(large_block=512, large_vec=2, large_depth=2, large_mode=0, precombine=32),
+    dict(large_block=512, large_vec=2, large_depth=4, large_mode=1, precombine=1),
+    dict(large_block=512, large_vec=3, large_depth=2, large_mode=0, precombine=8),
+    dict(large_block=1024, large_vec=2, large_depth=2, large_mode=1, precombine=8),
 ]
 
 
