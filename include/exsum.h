@@ -24,8 +24,8 @@
  * beyond 8 bytes, and every call is asynchronous on `stream` (a hipStream_t
  * passed as void*; NULL is the null stream): results are valid once the
  * stream reaches the call.  The library keeps a small per-(device, stream)
- * workspace (accumulators and tickets, under 64 KiB plus 1 KiB per
- * segment of the largest segmented call) that it allocates on the first call
+ * workspace (merge rows, accumulators and tickets, about 10 MiB) that it
+ * allocates on the first call
  * on that stream, zero-initialises synchronously, and keeps clean itself
  * (each call leaves it zeroed); exsum_release() frees it.  Calls on the same
  * stream are ordered; calls on different streams use different workspaces
@@ -77,19 +77,20 @@ int exsum_f64(const double *x, int64_t n, double *out, void *stream);
  * exsum_segmented_f64 -- out[i] = exact sum of x[offsets[i] .. offsets[i+1])
  * for 0 <= i < nseg, all in one persistent launch.
  *
- * Many independent exact sums (same definition as exsum_f64).  Each segment
- * takes the small-superaccumulator path or the large-plus-small path by its
- * length (Performance evaluations: the small method wins below about a
- * thousand terms, the large one above); long segments are split into tiles
- * whose small superaccumulators are merged per segment.
+ * Many independent exact sums (same definition as exsum_f64), one launch.
+ * Workgroups take equal shares of the concatenated terms; each piece of a
+ * segment takes the small-superaccumulator path (one wavefront) or the
+ * large-plus-small path (a workgroup) by its length (Performance
+ * evaluations: the small method wins for short sums, the large one for long
+ * sums); a segment cut by workgroup boundaries is merged from its pieces.
  *   x       : terms, device memory.
  *   offsets : nseg+1 int64 values, device memory, non-decreasing;
  *             offsets[0] need not be 0.  Not checked on the device.
  *   nseg    : number of segments, >= 0.  An empty segment sums to +0.0.
  *   out     : nseg binary64 results, device memory.
- * The call plans on the device (no host synchronisation) and may be captured
- * in a HIP graph after one warm-up call on the same stream with an nseg at
- * least as large (the warm-up sizes the workspace).
+ * Nothing is planned on the host and nothing synchronises; after one call on
+ * a stream (which allocates that stream's workspace) the call may be
+ * captured in a HIP graph.
  */
 int exsum_segmented_f64(const double *x, const int64_t *offsets, int64_t nseg,
                         double *out, void *stream);
@@ -123,9 +124,10 @@ int exsum_inexact_f64(const double *x, int64_t n, double *out, void *stream);
  *                 added with a single LDS update; 0 disables the pre-combine.
  *   small_max   : inputs with n <= small_max use the small-only kernel.
  *   small_grid  : workgroups of the small-only kernel; 0 = automatic.
- *   seg_small_max : segments with length <= seg_small_max take the
- *                   small-only path inside exsum_segmented_f64.
- *   seg_tile    : terms per work unit of a long segment (multiple of 4096).
+ *   seg_grid    : workgroups of the segmented kernel; 0 = one per compute unit.
+ *   seg_small_max : segment pieces of at most this many terms are summed by
+ *                   one wavefront with the small accumulator alone; longer
+ *                   ones by a workgroup with the large accumulator.
  */
 typedef struct {
     int32_t large_block;
@@ -138,7 +140,6 @@ typedef struct {
     int32_t small_grid;
     int32_t seg_grid;
     int64_t seg_small_max;
-    int64_t seg_tile;
 } exsum_config;
 
 /* Current configuration of the calling process (defaults until set). */

@@ -50,7 +50,6 @@ class ExsumConfig(ctypes.Structure):
         ("small_grid", ctypes.c_int32),
         ("seg_grid", ctypes.c_int32),
         ("seg_small_max", ctypes.c_int64),
-        ("seg_tile", ctypes.c_int64),
     ]
 
     def as_dict(self):

@@ -28,8 +28,7 @@ exsum_config default_config() {
   c.small_max = 4096;
   c.small_grid = 0;
   c.seg_grid = 0;
-  c.seg_small_max = 2048;
-  c.seg_tile = 65536;
+  c.seg_small_max = 4096;
   return c;
 }
 
@@ -45,8 +44,7 @@ bool config_ok(const exsum_config &c) {
   if (c.precombine < 0 || c.precombine > 64) return false;
   if (c.small_max < 0 || c.small_grid < 0 || c.small_grid > kMaxGrid) return false;
   if (c.seg_grid < 0 || c.seg_grid > kMaxGrid) return false;
-  if (c.seg_small_max < 0 || c.seg_small_max > 65536) return false;
-  if (c.seg_tile < 4096 || c.seg_tile % 4096 != 0 || c.seg_tile > (int64_t(1) << 30)) return false;
+  if (c.seg_small_max < 0 || c.seg_small_max > (int64_t(1) << 20)) return false;
   return true;
 }
 
@@ -182,37 +180,22 @@ int exsum_segmented_f64(const double *x, const int64_t *offsets, int64_t nseg, d
   int st = get_workspace(s, &w, &dev);
   if (st != EXSUM_OK) return st;
   int grid = c.seg_grid;
-  if (grid == 0) grid = 3 * cu_count(dev);
-  int64_t cap = 0;
-  void *ws = nullptr;
+  if (grid == 0) grid = cu_count(dev);
+  GlobalAcc *accs = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    if (w->seg_cap < nseg) {
-      if (w->seg) {
-        // the previous workspace may still be in use by work on this stream
-        hipError_t e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return status_of(e);
-        (void)hipFree(w->seg);
-        w->seg = nullptr;
-        w->seg_bytes = 0;
-        w->seg_cap = 0;
-      }
-      const int64_t new_cap = std::max<int64_t>(nseg, 1024);
-      const size_t bytes = seg_workspace_bytes(new_cap);
+    if (w->seg_accs == nullptr) {
       void *p = nullptr;
+      const size_t bytes = global_acc_bytes() * (size_t)kMaxGrid;
       hipError_t e = hipMalloc(&p, bytes);
       if (e != hipSuccess) return status_of(e);
       e = hipMemset(p, 0, bytes);
       if (e != hipSuccess) { (void)hipFree(p); return status_of(e); }
-      w->seg = p;
-      w->seg_bytes = bytes;
-      w->seg_cap = new_cap;
+      w->seg_accs = reinterpret_cast<GlobalAcc *>(p);
     }
-    cap = w->seg_cap;
-    ws = w->seg;
+    accs = w->seg_accs;
   }
-  return status_of(launch_segmented(x, offsets, nseg, out, ws, cap, s, grid, c.seg_small_max, c.seg_tile,
-                                    c.precombine));
+  return status_of(launch_segmented(x, offsets, nseg, out, accs, s, grid, c.seg_small_max, c.precombine));
 }
 
 int exsum_get_config(exsum_config *cfg) {
@@ -238,8 +221,8 @@ int exsum_release(void) {
     (void)hipSetDevice(kv.first.first);
     hipError_t e = hipFree(kv.second.rows);
     if (first == hipSuccess) first = e;
-    if (kv.second.seg) {
-      e = hipFree(kv.second.seg);
+    if (kv.second.seg_accs) {
+      e = hipFree(kv.second.seg_accs);
       if (first == hipSuccess) first = e;
     }
     (void)hipSetDevice(cur);

@@ -390,60 +390,14 @@ __device__ __forceinline__ void final_flush(LargeShared &S) {
 }
 
 // ---------------------------------------------------------------------------
-// Merge (Discussion: add the parts' small superaccumulators, round once).
-// A workgroup adds its 67 chunks into `g` with 64-bit integer atomics (exact
-// and order independent), takes a ticket, and the one that completes the
-// expected count reads and clears `g`, rounds, and writes *out.  Called by
-// every thread; returns true in the workgroup that wrote the result.
+// Cross-workgroup hand-over.  Everything one workgroup hands to another goes
+// through device-coherent accesses (agent-scope atomic loads, stores and
+// read-modify-writes, which the hardware performs at the device's coherence
+// point rather than in a per-die cache), and each producer waits for its
+// accesses to complete before it takes a ticket.  That orders the hand-over
+// without device-wide cache write-back or invalidation (several microseconds
+// each here).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool merge_and_round(long long *s_small, unsigned long long *spec,
-                                                unsigned int *s_ticket, unsigned int *s_D,
-                                                GlobalAcc *__restrict__ g, unsigned int expected,
-                                                double *__restrict__ out) {
-  const int tid = threadIdx.x;
-  __syncthreads();
-  if (expected <= 1) {
-    if (tid == 0) out[0] = __longlong_as_double((long long)round_chunks(s_small, spec[0], spec[1], spec[2], s_D));
-    __syncthreads();
-    return true;
-  }
-  if (tid < kSChunks) {
-    const long long v = s_small[tid];
-    if (v) atomicAdd(&g->chunk[tid], (unsigned long long)v);
-  }
-  if (tid == 0) {
-    if (spec[0]) atomicOr(&g->pos_inf, 1ull);
-    if (spec[1]) atomicOr(&g->neg_inf, 1ull);
-    if (spec[2]) atomicMax(&g->nan_bits, spec[2]);
-  }
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) *s_ticket = atomicAdd(&g->ticket, 1u);
-  __syncthreads();
-  const bool last = (*s_ticket == expected - 1);
-  __syncthreads();
-  if (!last) return false;
-  __threadfence();
-  if (tid < kSChunks) s_small[tid] = (long long)atomicExch(&g->chunk[tid], 0ull);
-  if (tid == 96) spec[0] = atomicExch(&g->pos_inf, 0ull);
-  if (tid == 97) spec[1] = atomicExch(&g->neg_inf, 0ull);
-  if (tid == 98) spec[2] = atomicExch(&g->nan_bits, 0ull);
-  if (tid == 99) atomicExch(&g->ticket, 0u);
-  __syncthreads();
-  if (tid == 0) out[0] = __longlong_as_double((long long)round_chunks(s_small, spec[0], spec[1], spec[2], s_D));
-  __syncthreads();
-  return true;
-}
-
-// Merge by rows (used by the one-sum kernels, where every workgroup of the
-// grid takes part).  Everything one workgroup hands to another goes through
-// device-coherent accesses (agent-scope atomic loads and stores, which the
-// hardware performs at the device's coherence point rather than in a
-// per-die cache), and each producer waits for its stores to complete before
-// it takes a ticket.  That orders the hand-over without device-wide cache
-// write-back or invalidation, which cost several microseconds each here.
-// Returns true in the workgroup that wrote *out.  Called by every thread
-// (block of at least 128 threads).
 __device__ __forceinline__ void coherent_store(long long *p, long long v) {
   __hip_atomic_store((unsigned long long *)p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -460,6 +414,99 @@ __device__ __forceinline__ unsigned int ticket_add(unsigned int *p) {
   return __hip_atomic_fetch_add(p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Merge into one accumulator (Discussion: add the parts' small
+// superaccumulators, round once).  A workgroup adds its 67 chunks into `g`
+// with 64-bit integer atomics (exact and order independent), takes a ticket,
+// and the one that completes the expected count reads and clears `g`, rounds,
+// and writes *out.  Called by every thread; returns true in the workgroup
+// that wrote the result.  Used where few parts meet (a segment cut by
+// workgroup boundaries), so the atomics see little contention.
+__device__ __forceinline__ bool merge_and_round(long long *s_small, unsigned long long *spec,
+                                                unsigned int *s_ticket, unsigned int *s_D,
+                                                GlobalAcc *__restrict__ g, unsigned int expected,
+                                                double *__restrict__ out) {
+  const int tid = threadIdx.x;
+  __syncthreads();
+  if (expected <= 1) {
+    if (tid < 64) {
+      const unsigned long long r = round_chunks_wave(s_small, spec[0], spec[1], spec[2], s_D, tid);
+      if (tid == 0) out[0] = __longlong_as_double((long long)r);
+    }
+    __syncthreads();
+    return true;
+  }
+  if (tid < kSChunks) {
+    const long long v = s_small[tid];
+    if (v) atomicAdd(&g->chunk[tid], (unsigned long long)v);
+  }
+  if (tid == 0) {
+    if (spec[0]) atomicOr(&g->pos_inf, 1ull);
+    if (spec[1]) atomicOr(&g->neg_inf, 1ull);
+    if (spec[2]) atomicMax(&g->nan_bits, spec[2]);
+  }
+  wait_memory();
+  __syncthreads();
+  if (tid == 0) *s_ticket = ticket_add(&g->ticket);
+  __syncthreads();
+  const bool last = (*s_ticket == expected - 1);
+  __syncthreads();
+  if (!last) return false;
+  if (tid < kSChunks) s_small[tid] = (long long)atomicExch(&g->chunk[tid], 0ull);
+  if (tid == 96) spec[0] = atomicExch(&g->pos_inf, 0ull);
+  if (tid == 97) spec[1] = atomicExch(&g->neg_inf, 0ull);
+  if (tid == 98) spec[2] = atomicExch(&g->nan_bits, 0ull);
+  if (tid == 99) atomicExch(&g->ticket, 0u);
+  __syncthreads();
+  if (tid < 64) {
+    const unsigned long long r = round_chunks_wave(s_small, spec[0], spec[1], spec[2], s_D, tid);
+    if (tid == 0) out[0] = __longlong_as_double((long long)r);
+  }
+  __syncthreads();
+  return true;
+}
+
+// The same for a single wavefront's small accumulator (acc: 68 chunks in
+// LDS, spec: 3 words, D: 70 words of scratch).  All 64 lanes call it.
+__device__ __forceinline__ void wave_merge_and_round(long long *acc, unsigned long long *spec, unsigned int *D,
+                                                     GlobalAcc *__restrict__ g, unsigned int expected,
+                                                     double *__restrict__ out, int lane) {
+  if (expected > 1) {
+    const long long v0 = acc[lane];
+    if (v0) atomicAdd(&g->chunk[lane], (unsigned long long)v0);
+    if (lane < 3) {
+      const long long v1 = acc[64 + lane];
+      if (v1) atomicAdd(&g->chunk[64 + lane], (unsigned long long)v1);
+    }
+    if (lane == 0) {
+      if (spec[0]) atomicOr(&g->pos_inf, 1ull);
+      if (spec[1]) atomicOr(&g->neg_inf, 1ull);
+      if (spec[2]) atomicMax(&g->nan_bits, spec[2]);
+    }
+    wait_memory();
+    unsigned int tk = 0;
+    if (lane == 0) tk = ticket_add(&g->ticket);
+    tk = (unsigned int)__builtin_amdgcn_readfirstlane((int)tk);
+    if (tk != expected - 1) return;
+    acc[lane] = (long long)atomicExch(&g->chunk[lane], 0ull);
+    if (lane < 3) acc[64 + lane] = (long long)atomicExch(&g->chunk[64 + lane], 0ull);
+    if (lane == 0) {
+      spec[0] = atomicExch(&g->pos_inf, 0ull);
+      spec[1] = atomicExch(&g->neg_inf, 0ull);
+      spec[2] = atomicExch(&g->nan_bits, 0ull);
+      atomicExch(&g->ticket, 0u);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  }
+  const unsigned long long r = round_chunks_wave(acc, spec[0], spec[1], spec[2], D, lane);
+  if (lane == 0) out[0] = __longlong_as_double((long long)r);
+}
+
+// Merge by rows (used by the one-sum kernels, where every workgroup of the
+// grid takes part, so a shared accumulator would see heavy atomic
+// contention).  Each workgroup stores its small accumulator as a row; groups
+// of kMergeGroup rows are summed by the group's last arrival and the group
+// sums by the last group.  Returns true in the workgroup that wrote *out.
+// Called by every thread (block of at least 128 threads).
 // Combine word w of rows [r0, r0+nr) of a row array: chunk words add, the
 // infinity flags OR, the NaN word takes the unsigned maximum.  Sixteen loads
 // are in flight at a time.
@@ -495,7 +542,10 @@ __device__ __forceinline__ bool merge_rows_and_round(long long *s_small, unsigne
   const unsigned int G = gridDim.x, b = blockIdx.x;
   __syncthreads();
   if (G == 1) {
-    if (tid == 0) out[0] = __longlong_as_double((long long)round_chunks(s_small, spec[0], spec[1], spec[2], s_D));
+    if (tid < 64) {
+      const unsigned long long r = round_chunks_wave(s_small, spec[0], spec[1], spec[2], s_D, tid);
+      if (tid == 0) out[0] = __longlong_as_double((long long)r);
+    }
     __syncthreads();
     return true;
   }
@@ -524,7 +574,10 @@ __device__ __forceinline__ bool merge_rows_and_round(long long *s_small, unsigne
   }
   if (tid == 0) __hip_atomic_store(&M->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
-  if (tid == 0) out[0] = __longlong_as_double((long long)round_chunks(s_small, spec[0], spec[1], spec[2], s_D));
+  if (tid < 64) {
+      const unsigned long long r = round_chunks_wave(s_small, spec[0], spec[1], spec[2], s_D, tid);
+      if (tid == 0) out[0] = __longlong_as_double((long long)r);
+    }
   __syncthreads();
   return true;
 }

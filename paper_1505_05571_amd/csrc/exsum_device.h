@@ -233,4 +233,116 @@ __device__ inline unsigned long long round_chunks(const long long *c, unsigned l
   return sign | (E << 52) | (q - (1ull << 52));
 }
 
+// ---- wave-parallel carry propagation and rounding -------------------------
+
+__device__ __forceinline__ unsigned int readlane_u32(unsigned int v, int lane) {
+  return (unsigned int)__builtin_amdgcn_readlane((int)v, lane);
+}
+
+// One parallel carry step on the 67 chunks held as digit i = A (lane i) for
+// i < 64 and digit 64 + j = B (lane j) for j < 3:  c_i <- low32(c_i) +
+// (c_{i-1} >> 32); the top digit (66) keeps its high part.  Value unchanged.
+__device__ __forceinline__ void carry_step_regs(long long &A, long long &B, int lane) {
+  const long long hiA = A >> 32, hiB = B >> 32;
+  const long long loA = A & 0xFFFFFFFFll, loB = B & 0xFFFFFFFFll;
+  long long cA = (long long)__shfl_up((unsigned long long)hiA, 1, 64);
+  if (lane == 0) cA = 0;
+  const long long hiA63 = (long long)readlane_u64((unsigned long long)hiA, 63);
+  long long cB = (long long)__shfl_up((unsigned long long)hiB, 1, 64);
+  if (lane == 0) cB = hiA63;
+  A = loA + cA;
+  if (lane < 2) B = loB + cB;
+  else if (lane == 2) B = B + cB;
+  else B = 0;
+}
+
+// Round sum c[i] 2^(32i-1075) (67 int64 chunks in LDS, |c[i]| < 2^62) to
+// binary64 bits, ties to even; specials take precedence.  Called by one
+// whole wavefront (all 64 lanes active); returns the same bits in every
+// lane.  Two parallel carry steps leave every digit below the top in
+// [-1, 2^32]; in the rare case that a digit sits exactly on a bound the
+// serial routine finishes the job (lane 0, D = 70 words of scratch).
+__device__ inline unsigned long long round_chunks_wave(const long long *c, unsigned long long pos_inf,
+                                                       unsigned long long neg_inf, unsigned long long nan_bits,
+                                                       unsigned int *D, int lane) {
+  if (nan_bits) return nan_bits | (1ull << 51);
+  if (pos_inf && neg_inf) return 0x7FF8000000000000ull;
+  if (pos_inf) return 0x7FF0000000000000ull;
+  if (neg_inf) return 0xFFF0000000000000ull;
+  long long A = c[lane];
+  long long B = (lane < 3) ? c[64 + lane] : 0;
+  carry_step_regs(A, B, lane);
+  carry_step_regs(A, B, lane);
+  // digits 0..65 now in [-1, 2^32]; a digit on either bound would need a
+  // longer carry chain
+  const bool edgeA = (A < 0) || (A > 0xFFFFFFFFll);
+  const bool edgeB = (lane < 2) && ((B < 0) || (B > 0xFFFFFFFFll));
+  if (__ballot(edgeA || edgeB) != 0ull) {
+    unsigned long long r = 0;
+    if (lane == 0) r = round_chunks(c, 0ull, 0ull, 0ull, D);
+    return readlane_u64(r, 0);
+  }
+  const long long top = (long long)readlane_u64((unsigned long long)B, 2);
+  unsigned int dA = (unsigned int)A;            // digits 0..63
+  unsigned int dB = (lane < 2) ? (unsigned int)B : 0u;  // digits 64, 65
+  long long mtop = top;
+  unsigned long long sign = 0;
+  if (top < 0) {
+    // two's-complement negation: digits below the lowest nonzero one stay 0,
+    // that digit becomes 2^32 - d, the digits above are complemented, and the
+    // top becomes -top - 1 (or -top if every lower digit is zero)
+    sign = 1ull << 63;
+    const unsigned long long nzA = __ballot(dA != 0u);
+    const unsigned long long nzB = __ballot(lane < 2 && dB != 0u);
+    int k;
+    if (nzA) k = __ffsll((long long)nzA) - 1;
+    else if (nzB) k = 64 + __ffsll((long long)nzB) - 1;
+    else k = 66;
+    const int iA = lane, iB = 64 + lane;
+    dA = (iA < k) ? 0u : (iA == k ? 0u - dA : ~dA);
+    if (lane < 2) dB = (iB < k) ? 0u : (iB == k ? 0u - dB : ~dB);
+    mtop = (k == 66) ? -top : -top - 1;
+  }
+  // magnitude digits: dA (0..63), dB (64, 65), mtop (66, small, >= 0)
+  const unsigned long long mA = __ballot(dA != 0u);
+  const unsigned long long mB = __ballot(lane < 2 && dB != 0u);
+  int t;
+  if (mtop != 0) t = 66;
+  else if (mB) t = 64 + (63 - __clzll((long long)mB));
+  else if (mA) t = 63 - __clzll((long long)mA);
+  else return 0;                                   // exact zero -> +0.0
+  auto digit = [&](int i) -> unsigned int {
+    if (i < 0) return 0u;
+    if (i < 64) return readlane_u32(dA, i);
+    if (i < 66) return readlane_u32(dB, i - 64);
+    if (i == 66) return (unsigned int)mtop;
+    return 0u;
+  };
+  const unsigned int Dt = digit(t);
+  const int Bl = 32 * t + 32 - __clz(Dt);          // bit length of X (units 2^-1075)
+  if (Bl <= 53) {
+    const unsigned long long X = (unsigned long long)digit(0) | ((unsigned long long)digit(1) << 32);
+    return sign | (X >> 1);
+  }
+  const int sh = Bl - 53;
+  const int w = sh >> 5, o = sh & 31;
+  unsigned long long q = ((unsigned long long)digit(w) | ((unsigned long long)digit(w + 1) << 32)) >> o;
+  if (o) q |= (unsigned long long)digit(w + 2) << (64 - o);
+  q &= (1ull << 53) - 1;
+  const int rpos = sh - 1;
+  const int rw = rpos >> 5;
+  const unsigned int rd = digit(rw);
+  const unsigned int rbit = (rd >> (rpos & 31)) & 1u;
+  bool sticky = (rd & ((1u << (rpos & 31)) - 1u)) != 0u;
+  // any nonzero digit strictly below rw
+  const unsigned long long belowA = (rw >= 64) ? mA : (rw > 0 ? (mA & ((1ull << rw) - 1ull)) : 0ull);
+  const unsigned long long belowB = (rw > 64) ? (mB & ((1ull << (rw - 64)) - 1ull)) : 0ull;
+  sticky = sticky || belowA || belowB;
+  unsigned long long E = (unsigned long long)sh;
+  if (rbit && (sticky || (q & 1))) q += 1;
+  if (q == (1ull << 53)) { q = 1ull << 52; E += 1; }
+  if (E >= 2047) return sign | 0x7FF0000000000000ull;
+  return sign | (E << 52) | (q - (1ull << 52));
+}
+
 }  // namespace exsum

@@ -18,10 +18,8 @@ struct Workspace {
   double *partials = nullptr;          // per-workgroup partials of the inexact sum
   unsigned int *ticket = nullptr;      // ticket of the inexact sum
   int max_grid = 0;                    // capacity of `partials`
-  // segmented calls
-  void *seg = nullptr;                 // segment workspace (see kernels_seg.hip)
-  size_t seg_bytes = 0;
-  int64_t seg_cap = 0;                 // segments the workspace holds
+  // segmented calls: one accumulator per workgroup boundary (kMaxGrid)
+  GlobalAcc *seg_accs = nullptr;
 };
 
 // Launchers (kernels_sum.hip).  Return a hipError_t.
@@ -34,10 +32,9 @@ hipError_t launch_inexact(const double *x, int64_t n, double *partials, unsigned
                           double *out, hipStream_t s, int grid);
 
 // Segmented sums (kernels_seg.hip).
-size_t seg_workspace_bytes(int64_t cap);
+size_t global_acc_bytes();
 hipError_t launch_segmented(const double *x, const int64_t *offsets, int64_t nseg, double *out,
-                            void *ws, int64_t cap, hipStream_t s, int grid, int64_t small_max,
-                            int64_t tile, int precombine);
+                            GlobalAcc *accs, hipStream_t s, int grid, int64_t small_max, int precombine);
 
 size_t merge_rows_bytes();
 

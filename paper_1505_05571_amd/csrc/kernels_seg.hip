@@ -1,212 +1,177 @@
-// kernels_seg.hip -- many exact sums of uneven length in one persistent
-// launch (plus a small planning launch), gfx950.
+// kernels_seg.hip -- many exact sums of uneven length in one launch (gfx950).
 //
-// Planning (one thread per segment, no host round trip): a segment of length
-// L <= small_max goes on the short list; a longer one becomes a long entry
-// with ceil(L / tile) tiles.  The small/large choice follows the Performance
-// evaluations section (the small superaccumulator alone is faster for short
-// sums, the large one for long sums); the threshold is a tuning knob.
-//
-// Persistent kernel, two phases per workgroup:
-//   A. long tiles: thread 0 takes (entry, tile) from a two-level cursor; the
-//      whole workgroup adds the tile into its large accumulator in LDS,
-//      transfers it into the small accumulator (cleaning the LDS for the next
-//      tile), and merges into the segment's global accumulator; the tile that
-//      completes the segment rounds it.  A one-tile segment is rounded in
-//      place.
-//   B. short segments: each wavefront takes a batch of short segments and
-//      sums each with the small-only wave body, rounding in the wavefront.
-// The last workgroup to finish resets the cursors, so the workspace is clean
-// for the next call.
+// The segments x[offsets[i] .. offsets[i+1]) tile the range [offsets[0],
+// offsets[nseg]) of x.  Workgroup w of G takes the terms
+// [o0 + N*w/G, o0 + N*(w+1)/G)  (N = offsets[nseg] - offsets[0]; G is the
+// grid capped at N, so that no range is empty),
+// so every workgroup reads the same number of bytes whatever the lengths,
+// and no planning pass or work queue is needed.  It finds its first segment
+// with a wavefront-wide search of the offsets and walks the segments that
+// meet its range in batches of up to 256:
+//   * pieces of at most small_max terms are summed by single wavefronts with
+//     the small-superaccumulator body, wave v taking pieces v, v + NW, ...
+//     of the batch (the Performance evaluations find the small method the
+//     faster one for short sums).  The piece index is a plain scalar loop
+//     counter: a counter claimed by one lane and broadcast with
+//     readfirstlane is not safe here, since the compiler may route the other
+//     lanes round the loop without that lane;
+//   * longer pieces are summed by the whole workgroup with the large
+//     accumulator body (carry-triggered transfers, no tile barriers).
+// A segment inside one workgroup's range is rounded by that workgroup.  A
+// segment cut by range boundaries (at most one per boundary) is merged
+// through the accumulator slot of the first workgroup that meets it, with a
+// ticket counting its pieces; the piece that completes it rounds it.  An
+// empty segment is written (+0.0) by the workgroup whose range holds its
+// position (the last workgroup for position offsets[nseg]).
 #include "exsum_blocks.h"
 #include "exsum_internal.h"
 
 namespace exsum {
 namespace {
 
-struct SegHeader {
-  unsigned int nlong;       // long entries planned
-  unsigned int nshort;      // short segments planned
-  unsigned int long_cur;    // entry currently handed out
-  unsigned int short_cur;   // next short slot
-  unsigned int done;        // workgroups finished
-  unsigned int pad[59];
-};
-static_assert(sizeof(SegHeader) == 256, "SegHeader layout");
+constexpr int kSegBatch = 256;
 
-struct LongEntry {
-  int seg;
-  unsigned int ntiles;
-  unsigned int next_tile;
-  unsigned int pad;
-};
-
-struct SegLayout {
-  SegHeader *hdr;
-  LongEntry *entries;
-  int *short_ids;
-  GlobalAcc *accs;
-};
-
-__host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-__host__ __device__ inline SegLayout seg_layout(void *ws, long long nseg) {
-  SegLayout L;
-  char *p = static_cast<char *>(ws);
-  size_t off = 0;
-  L.hdr = reinterpret_cast<SegHeader *>(p + off);
-  off += sizeof(SegHeader);
-  L.entries = reinterpret_cast<LongEntry *>(p + off);
-  off = align_up(off + sizeof(LongEntry) * (size_t)nseg, 256);
-  L.short_ids = reinterpret_cast<int *>(p + off);
-  off = align_up(off + sizeof(int) * (size_t)nseg, 256);
-  L.accs = reinterpret_cast<GlobalAcc *>(p + off);
-  return L;
+// Workgroup of G whose term range contains relative position p (0 <= p < N):
+// the largest w with floor(N*w/G) <= p.
+__device__ __forceinline__ long long wg_of(long long p, long long N, long long G) {
+  return ((p + 1) * G + N - 1) / N - 1;
 }
 
-constexpr int kShortBatch = 8;
+struct SegShared {
+  LargeShared L;
+  long long off[kSegBatch + 1];        // a batch of segment offsets
+  long long wacc[16][68];              // per-wave small accumulators
+  unsigned long long wspec[16][4];     // per-wave side words
+  unsigned int wD[16][70];             // per-wave rounding scratch
+  unsigned int nb;                     // segments of this batch that meet the range
+  long long first;                     // first segment of the range
+};
 
-__global__ __launch_bounds__(256) void seg_plan_kernel(const long long *__restrict__ offsets, long long nseg,
-                                                       void *ws, long long cap, long long small_max,
-                                                       long long tile) {
-  SegLayout Lw = seg_layout(ws, cap);
-  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-  const int lane = threadIdx.x & 63;
-  long long L = 0;
-  if (i < nseg) L = offsets[i + 1] - offsets[i];
-  const bool is_short = (i < nseg) && (L <= small_max);
-  const bool is_long = (i < nseg) && (L > small_max);
-  // wave-aggregated slot allocation: one atomic per wave per list
-  const unsigned long long ms = __ballot(is_short);
-  const unsigned long long ml = __ballot(is_long);
-  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  unsigned int bs = 0, bl = 0;
-  if (lane == 0) {
-    if (ms) bs = atomicAdd(&Lw.hdr->nshort, (unsigned int)__popcll(ms));
-    if (ml) bl = atomicAdd(&Lw.hdr->nlong, (unsigned int)__popcll(ml));
-  }
-  bs = __shfl(bs, 0, 64);
-  bl = __shfl(bl, 0, 64);
-  if (is_short) Lw.short_ids[bs + __popcll(ms & below)] = (int)i;
-  if (is_long) {
-    LongEntry e;
-    e.seg = (int)i;
-    e.ntiles = (unsigned int)((L + tile - 1) / tile);
-    e.next_tile = 0u;
-    e.pad = 0u;
-    Lw.entries[bl + __popcll(ml & below)] = e;
-  }
-}
-
-template <int BLOCK, int VEC>
+template <int BLOCK, int VEC, int DEPTH>
 __global__ __launch_bounds__(BLOCK) void seg_kernel(const double *__restrict__ x,
                                                     const long long *__restrict__ offsets, long long nseg,
-                                                    double *__restrict__ out, void *ws, long long cap,
-                                                    long long tile_terms, int precombine) {
-  __shared__ LargeShared S;
-  SegLayout Lw = seg_layout(ws, cap);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  large_init(S, tid, BLOCK);
+                                                    double *__restrict__ out, GlobalAcc *__restrict__ accs,
+                                                    long long small_max, int precombine) {
+  static_assert(BLOCK / 64 <= 16, "per-wave LDS sized for 16 waves");
+  __shared__ SegShared S;
+  constexpr int NW = BLOCK / 64;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // all lanes active here
+  const long long o0 = offsets[0], oN = offsets[nseg];
+  const long long N = oN - o0;
+  // at most one workgroup per term, so every range is nonempty and a
+  // segment's pieces are exactly the workgroups wg_of(first) .. wg_of(last)
+  const long long G = ((long long)gridDim.x < N) ? (long long)gridDim.x : (N > 0 ? N : 1);
+  const long long w = blockIdx.x;
+  if (w >= G) return;                                   // whole workgroup, before any barrier
+  large_init(S.L, tid, BLOCK);
+  const long long lo_w = o0 + N * w / G, hi_w = o0 + N * (w + 1) / G;
+  const bool last_wg = (w == G - 1);
+
+  // first segment: i = j - 1 for the smallest j in [1, nseg] with
+  // offsets[j] >= lo_w (offsets[nseg] qualifies).  Wave 0 cuts the candidate
+  // interval [lo, hi] 64 ways per round.
+  if (wave == 0) {
+    long long lo = 1, hi = nseg;
+    while (hi - lo > 63) {
+      const long long span = hi - lo;
+      const long long p = lo + span * lane / 64;       // < hi
+      const unsigned long long m = __ballot(offsets[p] >= lo_w);
+      const int f = m ? (__ffsll((long long)m) - 1) : 64;
+      const long long nlo = (f == 0) ? lo : lo + span * (f - 1) / 64 + 1;
+      const long long nhi = (f == 64) ? hi : lo + span * f / 64;
+      lo = nlo;
+      hi = nhi;
+    }
+    const long long p = lo + lane;
+    const long long pc = p <= hi ? p : hi;
+    const unsigned long long m = __ballot(p <= hi && offsets[pc] >= lo_w);
+    const long long j = m ? lo + (__ffsll((long long)m) - 1) : hi;
+    if (lane == 0) S.first = j - 1;
+  }
   __syncthreads();
-  const unsigned int nlong = Lw.hdr->nlong;
-  const unsigned int nshort = Lw.hdr->nshort;
+  long long i = S.first;
   unsigned int tile = 0;
 
-  // phase A: tiles of long segments
-  while (nlong) {
-    if (tid == 0) {
-      unsigned int eidx = 0xFFFFFFFFu, t = 0;
-      while (true) {
-        const unsigned int cur = __hip_atomic_load(&Lw.hdr->long_cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (cur >= nlong) break;
-        t = atomicAdd(&Lw.entries[cur].next_tile, 1u);
-        if (t < Lw.entries[cur].ntiles) { eidx = cur; break; }
-        atomicCAS(&Lw.hdr->long_cur, cur, cur + 1u);
-      }
-      S.bcast[0] = eidx;
-      S.bcast[1] = t;
+  while (i < nseg) {
+    const int cnt = (int)((nseg - i < kSegBatch) ? (nseg - i) : kSegBatch);
+    for (int k = tid; k <= cnt; k += BLOCK) S.off[k] = offsets[i + k];
+    if (tid == 0) S.nb = (unsigned int)cnt;
+    __syncthreads();
+    // the segments of the batch that meet the range form a prefix
+    for (int k = tid; k < cnt; k += BLOCK) {
+      const long long s0 = S.off[k];
+      const bool beyond = last_wg ? (s0 > hi_w) : (s0 >= hi_w);
+      if (beyond) atomicMin(&S.nb, (unsigned int)k);
     }
     __syncthreads();
-    const unsigned int eidx = S.bcast[0], t = S.bcast[1];
-    __syncthreads();
-    if (eidx == 0xFFFFFFFFu) break;
-    const LongEntry e = Lw.entries[eidx];
-    const long long start = offsets[e.seg], end = offsets[e.seg + 1];
-    const long long r0 = start + (long long)t * tile_terms;
-    const long long r1 = (r0 + tile_terms < end) ? r0 + tile_terms : end;
-    accumulate_range<BLOCK, VEC, 2, kCountMode>(S, x, r0, r1, precombine, tile);
-    final_flush<BLOCK, true, kCountMode>(S);
-    merge_and_round(S.small, S.spec, &S.ticket, S.D, &Lw.accs[eidx], e.ntiles, &out[e.seg]);
-    if (tid < 68) S.small[tid] = 0;
-    if (tid < 3) S.spec[tid] = 0ull;
-    __syncthreads();
-  }
+    const int nb = (int)S.nb;
 
-  // phase B: short segments, one wavefront per segment, in batches
-  {
-    char *base = reinterpret_cast<char *>(&S.chunk[0]) + wave * 1024;
-    long long *acc = reinterpret_cast<long long *>(base);
-    unsigned long long *spec = reinterpret_cast<unsigned long long *>(base + 576);
-    unsigned int *D = reinterpret_cast<unsigned int *>(base + 640);
-    while (true) {
-      unsigned int j0 = 0;
-      if (lane == 0) j0 = atomicAdd(&Lw.hdr->short_cur, (unsigned int)kShortBatch);
-      j0 = __shfl(j0, 0, 64);
-      if (j0 >= nshort) break;
-      const unsigned int j1 = (j0 + kShortBatch < nshort) ? j0 + kShortBatch : nshort;
-      for (unsigned int j = j0; j < j1; j++) {
-        const int seg = Lw.short_ids[j];
+    // wave phase: short pieces
+    {
+      long long *acc = S.wacc[wave];
+      unsigned long long *spec = S.wspec[wave];
+      unsigned int *D = S.wD[wave];
+      for (int k = wave; k < nb; k += NW) {
+        const long long s0 = S.off[k], s1 = S.off[k + 1];
+        const long long a = s0 > lo_w ? s0 : lo_w;
+        const long long b = s1 < hi_w ? s1 : hi_w;
+        if (s0 != s1 && a >= b) continue;              // a nonempty segment this range misses
+        if (b - a > small_max) continue;               // a long piece: workgroup phase
         acc[lane] = 0;
         if (lane < 4) acc[64 + lane] = 0;
         if (lane < 3) spec[lane] = 0ull;
-        __builtin_amdgcn_wave_barrier();
-        small_wave_accumulate(acc, spec, x, offsets[seg], offsets[seg + 1], lane);
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        if (lane == 0) out[seg] = __longlong_as_double((long long)round_chunks(acc, spec[0], spec[1], spec[2], D));
-        __builtin_amdgcn_wave_barrier();
+        small_wave_accumulate(acc, spec, x, a, b, lane);
+        const bool split = (s0 < lo_w) || (s1 > hi_w);
+        unsigned int expected = 1;
+        GlobalAcc *g = nullptr;
+        if (split) {
+          const long long w1 = wg_of(s0 - o0, N, G);
+          expected = (unsigned int)(wg_of(s1 - 1 - o0, N, G) - w1 + 1);
+          g = &accs[w1];
+        }
+        wave_merge_and_round(acc, spec, D, g, expected, &out[i + k], lane);
       }
     }
-  }
+    __syncthreads();
 
-  // completion: the last workgroup resets the cursors for the next call
-  __syncthreads();
-  if (tid == 0) {
-    __threadfence();
-    const unsigned int d = atomicAdd(&Lw.hdr->done, 1u);
-    if (d == gridDim.x - 1) {
-      atomicExch(&Lw.hdr->nlong, 0u);
-      atomicExch(&Lw.hdr->nshort, 0u);
-      atomicExch(&Lw.hdr->long_cur, 0u);
-      atomicExch(&Lw.hdr->short_cur, 0u);
-      atomicExch(&Lw.hdr->done, 0u);
+    // workgroup phase: long pieces, in order
+    for (int k = 0; k < nb; k++) {
+      const long long s0 = S.off[k], s1 = S.off[k + 1];
+      const long long a = s0 > lo_w ? s0 : lo_w;
+      const long long b = s1 < hi_w ? s1 : hi_w;
+      if (b - a <= small_max) continue;
+      accumulate_range<BLOCK, VEC, DEPTH, kCarryMode>(S.L, x, a, b, precombine, tile);
+      final_flush<BLOCK, true, kCarryMode>(S.L);
+      const bool split = (s0 < lo_w) || (s1 > hi_w);
+      unsigned int expected = 1;
+      GlobalAcc *g = nullptr;
+      if (split) {
+        const long long w1 = wg_of(s0 - o0, N, G);
+        expected = (unsigned int)(wg_of(s1 - 1 - o0, N, G) - w1 + 1);
+        g = &accs[w1];
+      }
+      merge_and_round(S.L.small, S.L.spec, &S.L.ticket, S.L.D, g, expected, &out[i + k]);
+      if (tid < 68) S.L.small[tid] = 0;
+      if (tid < 3) S.L.spec[tid] = 0ull;
+      __syncthreads();
     }
+    if (nb < cnt) break;                               // the range ended inside this batch
+    i += cnt;
+    __syncthreads();
   }
 }
 
 }  // namespace
 
-// The layout depends only on the capacity (segments the workspace was sized
-// for), never on a call's nseg, so regions that must stay zero between calls
-// (the per-segment accumulators) never move.
-size_t seg_workspace_bytes(int64_t nseg) {
-  size_t off = sizeof(SegHeader);
-  off = align_up(off + sizeof(LongEntry) * (size_t)nseg, 256);
-  off = align_up(off + sizeof(int) * (size_t)nseg, 256);
-  off += sizeof(GlobalAcc) * (size_t)nseg;
-  return off;
-}
-
-hipError_t launch_segmented(const double *x, const int64_t *offsets, int64_t nseg, double *out, void *ws,
-                            int64_t cap, hipStream_t s, int grid, int64_t small_max, int64_t tile,
-                            int precombine) {
-  const int plan_blocks = (int)((nseg + 255) / 256);
-  hipLaunchKernelGGL(seg_plan_kernel, dim3(plan_blocks), dim3(256), 0, s, (const long long *)offsets,
-                     (long long)nseg, ws, (long long)cap, (long long)small_max, (long long)tile);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((seg_kernel<256, 4>), dim3(grid), dim3(256), 0, s, x, (const long long *)offsets,
-                     (long long)nseg, out, ws, (long long)cap, (long long)tile, precombine);
+hipError_t launch_segmented(const double *x, const int64_t *offsets, int64_t nseg, double *out, GlobalAcc *accs,
+                            hipStream_t s, int grid, int64_t small_max, int precombine) {
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL((seg_kernel<512, 4, 2>), dim3(grid), dim3(512), 0, s, x, (const long long *)offsets,
+                     (long long)nseg, out, accs, (long long)small_max, precombine);
   return hipGetLastError();
 }
+
+size_t global_acc_bytes() { return sizeof(GlobalAcc); }
 
 }  // namespace exsum

@@ -71,7 +71,7 @@ def test_config_roundtrip_and_validation(lib):
         ex.exsum_set_config(c)
         assert ex.exsum_get_config().large_mode == 1
         for field, bad in [("large_vec", 8), ("large_block", 128), ("precombine", -1), ("large_mode", 2),
-                           ("seg_tile", 1000), ("seg_small_max", 1 << 20), ("large_grid", -3)]:
+                           ("seg_small_max", 1 << 21), ("large_grid", -3)]:
             c = ex.exsum_get_config()
             setattr(c, field, bad)
             with pytest.raises(ex.ExsumError):

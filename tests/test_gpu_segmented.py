@@ -4,6 +4,7 @@ import numpy as np
 import pytest
 
 import oracle
+from chain_cases import long_chain_cases
 from paper_1505_05571_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -44,10 +45,11 @@ def seg_bits(ex, xt, offt, **kw):
 
 VARIANTS = [
     dict(),
-    dict(seg_small_max=0, seg_tile=4096),
-    dict(seg_small_max=65536, seg_tile=8192),
-    dict(seg_small_max=100, seg_tile=65536, seg_grid=5),
-    dict(seg_small_max=2048, seg_tile=4096 * 3, seg_grid=1),
+    dict(seg_small_max=0),
+    dict(seg_small_max=65536, seg_grid=37),
+    dict(seg_small_max=100, seg_grid=5),
+    dict(seg_small_max=2048, seg_grid=1),
+    dict(seg_small_max=4096, seg_grid=1000),
 ]
 
 
@@ -93,6 +95,26 @@ def test_hot_chunk_segments(ex):
         assert np.array_equal(seg_bits(ex, xt, offt, **v), want), v
 
 
+def test_long_carry_chain_segments(ex):
+    # each case once as a short segment and once spread over a long one that
+    # workgroup boundaries cut into pieces
+    parts, lens = [], []
+    for c in long_chain_cases():
+        parts.append(c)
+        lens.append(c.size)
+        big = np.zeros(150001, dtype=np.float64)
+        big[::150001 // c.size][:c.size] = c
+        parts.append(big)
+        lens.append(big.size)
+    x = np.concatenate(parts)
+    off = np.zeros(len(lens) + 1, dtype=np.int64)
+    np.cumsum(lens, out=off[1:])
+    want = oracle.segmented_f64(x, off)
+    xt, offt = dev(x), dev(off)
+    for v in VARIANTS:
+        assert np.array_equal(seg_bits(ex, xt, offt, **v), want), v
+
+
 def test_repeated_calls_and_shrinking_batches(ex):
     x, off = W.segments(nseg=5000, seed=5, hi=100000)
     xt = dev(x)
@@ -100,6 +122,19 @@ def test_repeated_calls_and_shrinking_batches(ex):
         o = off[:nseg + 1]
         want = oracle.segmented_f64(x, o)
         assert np.array_equal(seg_bits(ex, xt, dev(o)), want), nseg
+
+
+def test_fewer_terms_than_workgroups(ex):
+    # the kernel caps its grid at the number of terms; a segment cut into
+    # pieces must count exactly the workgroups that hold one
+    x = W.uniform_exponent(300, seed=11)
+    for off in ([0, 5, 9, 300], [0, 1], [3, 3, 3], [0, 0, 201, 201], [299, 300]):
+        o = np.array(off, dtype=np.int64)
+        want = oracle.segmented_f64(x, o)
+        xt, offt = dev(x), dev(o)
+        for grid in (0, 1, 2, 200, 1000, 8192):
+            assert np.array_equal(seg_bits(ex, xt, offt, seg_grid=grid), want), (off, grid)
+            assert np.array_equal(seg_bits(ex, xt, offt, seg_grid=grid, seg_small_max=0), want), (off, grid)
 
 
 def test_full_size_batched_workload(ex):

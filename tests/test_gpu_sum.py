@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
+from chain_cases import long_chain_cases
 from paper_1505_05571_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -188,6 +189,19 @@ def test_denormals_and_extremes(ex):
     want = int(oracle.sum_f64(top))
     for c in all_paths(ex)[:8]:
         assert run(ex, top, c) == want
+
+
+def test_long_carry_chains(ex):
+    for x in long_chain_cases():
+        want = int(oracle.sum_f64(x))
+        for c in all_paths(ex)[:9]:
+            assert run(ex, x, c) == want, (x, c.as_dict())
+        # the same value spread over a long input (the large path proper)
+        big = np.zeros(200003, dtype=np.float64)
+        big[::200003 // x.size][:x.size] = x
+        assert int(oracle.sum_f64(big)) == want
+        for c in all_paths(ex)[:9]:
+            assert run(ex, big, c) == want, (x, c.as_dict())
 
 
 def test_permutation_invariance(ex):
