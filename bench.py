@@ -11,16 +11,19 @@ uniform in [1, 2) and exponent uniform in [-300, 300], resident in HBM before
 the timed region starts.  Prints ONE JSON line.
 
 Besides the throughput, the line carries:
-  * ``roofline``: the large-accumulator kernel's algorithmic bytes (8 per
-    term) over its average duration, measured with HIP events on the stream
-    it runs on, against the 8 TB/s HBM peak; ``traffic`` is the HBM bytes per
+  * ``roofline``: the kernel's algorithmic bytes (8 per term) over its
+    average duration (HIP events on the stream it runs on, around the K
+    back-to-back timed launches), against the 8 TB/s HBM peak; ``traffic`` is the HBM bytes per
     launch from rocprofv3 counters (profiles/) when they were taken on the
     current kernel source, else null;
   * ``inexact``: the same data summed by an ordinary (inexact) HIP tree sum
     and by torch.sum, and the time ratio exact/inexact;
   * ``cpu_baseline``: the CPU oracle (plain wide-integer sum) timed on the
     host cores on the same array;
-  * ``parity``: whether the GPU bits equal the oracle's.
+  * ``parity``: whether the GPU bits equal the oracle's;
+  * ``latency_ms``: single-call device time (events around each call) and
+    host time (call + synchronize), p50 and p99, measured after the timed
+    region.
 """
 from __future__ import annotations
 
@@ -182,17 +185,34 @@ def main():
         step(i)
     torch.cuda.synchronize()
 
-    # timed region: exactly K steps, each bracketed by events on the kernel's stream
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    # timed region: exactly K steps, launched back to back; one pair of HIP
+    # events on the kernel's stream brackets them (per-step events would add
+    # the dispatch gap between launches to every kernel's time)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    ev0.record(stream)
     for i in range(args.steps):
+        step(i)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    avg_kernel_s = ev0.elapsed_time(ev1) / 1e3 / args.steps
+
+    # latency of single calls, outside the timed region: device time between
+    # events around each call, and host time of call + stream synchronize
+    ncalls = 2000 if n <= 100000 else max(args.steps, 20)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(ncalls)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(ncalls)]
+    host_ms = np.empty(ncalls)
+    for i in range(ncalls):
+        h0 = time.perf_counter()
         starts[i].record(stream)
         step(i)
         ends[i].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+        stream.synchronize()
+        host_ms[i] = (time.perf_counter() - h0) * 1e3
     ev_ms = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
 
     # parity of the timed result against the oracle
@@ -207,7 +227,6 @@ def main():
 
     bytes_per_step = 8.0 * n
     value = bytes_per_step * args.steps / wall / 1e9
-    avg_kernel_s = float(ev_ms.mean()) / 1e3
     achieved = bytes_per_step / avg_kernel_s / 1e9
     traffic = read_traffic() if args.workload == "uniform_exponent" else None
 
@@ -249,8 +268,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "n_terms": n, "input_dtype": "f64", "seed": 0,
                    "terms_per_s": round(n * args.steps / wall, 1)},
-        "latency_ms": {"p50": round(float(np.percentile(ev_ms, 50)), 4),
-                       "p99": round(float(np.percentile(ev_ms, 99)), 4)},
+        "latency_ms": {"calls": ncalls,
+                       "device_p50": round(float(np.percentile(ev_ms, 50)), 4),
+                       "device_p99": round(float(np.percentile(ev_ms, 99)), 4),
+                       "host_p50": round(float(np.percentile(host_ms, 50)), 4),
+                       "host_p99": round(float(np.percentile(host_ms, 99)), 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
         "inexact": inexact,

@@ -276,6 +276,13 @@ __device__ __forceinline__ ulonglong2 stream_load(const ulonglong2 *p) {
   return make_ulonglong2(v.x, v.y);
 }
 
+// Target of the prefetches issued past a stream's last tile (their values are
+// never used).  Small and read by every wave, so it stays in L2: pointing
+// them here instead of at input already read keeps the kernel's HBM traffic
+// at one read of the input.
+constexpr int kMaxVec = 8;
+static __device__ ulonglong2 g_pad_tile[64 * kMaxVec];
+
 // Add x[r0 .. r1) into the workgroup's large accumulator.  A misaligned first
 // term and an odd last term are added as scalars.  The 16-byte vectors are
 // split into one contiguous stream per wavefront; a wave's tile is 64*VEC
@@ -310,14 +317,15 @@ __device__ __forceinline__ void accumulate_range(LargeShared &S, const double *_
   const long long ws = (long long)wave * q;
   const long long we = (wave == NW - 1) ? nv : ws + q;
   const long long ntiles = q / TILE_W;               // full tiles, the same for every wave
-  // Loads are unconditional (an index past the last tile re-reads the last
-  // tile) so the compiler's wait counts stay exact and a prefetch is never
-  // waited for early.
+  // Loads are unconditional (an index past the last tile reads the pad tile)
+  // so the compiler's wait counts stay exact and a prefetch is never waited
+  // for early.
+  static_assert(VEC <= kMaxVec, "pad tile too small");
   ulonglong2 buf[DEPTH][VEC];
   auto load = [&](ulonglong2(&bf)[VEC], long long t) {
-    const long long tb = ws + (t < ntiles ? t : ntiles - 1) * TILE_W + lane;
+    const ulonglong2 *tp = (t < ntiles) ? xv + ws + t * TILE_W : g_pad_tile;
 #pragma unroll
-    for (int j = 0; j < VEC; j++) bf[j] = stream_load(&xv[tb + j * 64]);
+    for (int j = 0; j < VEC; j++) bf[j] = stream_load(&tp[lane + j * 64]);
     // keep the scheduler from hoisting work on other buffers above these
     // loads (which would force an early wait on them)
     __builtin_amdgcn_sched_barrier(0);
