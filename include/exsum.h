@@ -154,6 +154,100 @@ int exsum_f64_cfg(const double *x, int64_t n, double *out, void *stream,
 /* Free every cached workspace (call with no exsum work in flight). */
 int exsum_release(void);
 
+/* ------------------------------------------------------------------------
+ * Serving loop: many independent exact sums (requests) arriving over time,
+ * served by continuous batching on one stream.
+ *
+ * A request is a range of device memory (x, n) and a device slot for its
+ * one binary64 result; its result is the same bits as exsum_f64(x, n) gives
+ * (the exact sum, rounded once), whatever else is in flight.  Each step
+ * takes a budget of terms from the active requests in arrival order: first
+ * one piece (up to piece_terms) for every active request, then more pieces
+ * for the oldest requests; a request of at most piece_terms terms is never
+ * split.  One kernel launch sums the step's pieces; a request cut into
+ * pieces adds them into an integer accumulator slot (Discussion, on adding
+ * the small superaccumulators of parts) and the last piece rounds.  A
+ * request is complete when the step holding its last piece has completed on
+ * the stream (observed with events by exsum_server_poll).
+ *
+ * The server owns: its accumulator slots (max_slots x 576 bytes of device
+ * memory), pinned host and device piece tables (max_inflight x max_pieces x
+ * 32 bytes each) and events, all allocated by exsum_server_create.  The
+ * caller owns x and out and keeps them alive until the request completes.
+ * A server is used from one host thread at a time.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t step_terms;    /* term budget of one step, >= piece_terms (default 2^26) */
+    int64_t piece_terms;   /* most terms in one piece, >= 1 (default 2^17) */
+    int64_t short_max;     /* pieces of at most this many terms are summed by one
+                              wavefront, the others by one workgroup (default 4096) */
+    int32_t max_slots;     /* requests cut into pieces that may be active at once,
+                              1 .. 2^20 (default 4096); more wait for admission */
+    int32_t max_pieces;    /* most pieces in one step, 1 .. 2^20 (default 16384) */
+    int32_t max_inflight;  /* steps queued on the stream at once, 1 .. 64 (default 2) */
+    int32_t precombine;    /* as in exsum_config (default 16) */
+} exsum_server_config;
+
+typedef struct exsum_server exsum_server;
+
+/* Fill *cfg with the defaults. */
+int exsum_server_default_config(exsum_server_config *cfg);
+
+/* Create a server on the current device that launches on `stream`.
+   EXSUM_EINVAL for a bad configuration, EXSUM_ENOMEM / EXSUM_EDEVICE if an
+   allocation fails (nothing is left allocated then). */
+int exsum_server_create(const exsum_server_config *cfg, void *stream, exsum_server **out);
+
+/* Wait for the server's work to finish and free everything it owns. */
+int exsum_server_destroy(exsum_server *srv);
+
+/* Queue one request: the exact sum of x[0..n) into *out (device pointers).
+   *id receives the request's id (0, 1, 2, ... in submission order).
+   EXSUM_EINVAL for n < 0, n >= 2^40, a NULL out, or a NULL x with n > 0. */
+int exsum_server_submit(exsum_server *srv, const double *x, int64_t n, double *out, int64_t *id);
+
+/* Plan and launch one step if there is work and fewer than max_inflight
+   steps are queued; *launched = number of pieces launched (0 if none).
+   Never blocks. */
+int exsum_server_step(exsum_server *srv, int64_t *launched);
+
+/* Ids of requests completed since the previous call, in completion order:
+   up to `max` into ids[0..*count).  Never blocks. */
+int exsum_server_poll(exsum_server *srv, int64_t *ids, int64_t max, int64_t *count);
+
+/* Step and wait until every submitted request is complete (completed ids
+   stay available to exsum_server_poll). */
+int exsum_server_drain(exsum_server *srv);
+
+/* Requests submitted and not yet reported complete. */
+int exsum_server_pending(exsum_server *srv, int64_t *count);
+
+/* Replay a trace in real time through the server.  Request i sums
+   pool[starts[i] .. starts[i]+lens[i]) into out[i] and arrives arrival_s[i]
+   seconds after the replay starts (non-decreasing).  latency_s[i] receives
+   the time from its arrival to the host observing its completion;
+   *makespan_s the time from the start to the last completion.  pool and out
+   are device memory; starts, lens, arrival_s and latency_s host memory. */
+int exsum_server_replay(exsum_server *srv, const double *pool, const int64_t *starts, const int64_t *lens,
+                        const double *arrival_s, int64_t nreq, double *out, double *latency_s,
+                        double *makespan_s);
+
+/* The same trace served without batching: each request is one exsum_f64
+   call, launched on `stream` when it arrives (first in, first out). */
+int exsum_serial_replay(const double *pool, const int64_t *starts, const int64_t *lens,
+                        const double *arrival_s, int64_t nreq, double *out, void *stream,
+                        double *latency_s, double *makespan_s);
+
+/* The server's scheduling plan, on the host only (no device work): requests
+   of the given lengths all submitted at once, steps planned until every
+   term is scheduled, each step's slots released before the next.  Writes
+   up to `cap` pieces (request, offset, length, step, slot, expected count
+   or 0xFFFFFFFF for a piece of a step that does not complete its request)
+   and the total number of pieces to *count. */
+int exsum_server_plan(const exsum_server_config *cfg, const int64_t *lens, int64_t nreq, int64_t cap,
+                      int64_t *req, int64_t *off, int64_t *len, int64_t *step, int32_t *slot,
+                      uint32_t *expected, int64_t *count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,6 +15,7 @@ __all__ = [
     "ExsumError", "ExsumConfig", "library_path", "load_library",
     "exsum_f64", "exsum_segmented_f64", "exsum_inexact_f64", "exsum_f64_cfg",
     "exsum_get_config", "exsum_set_config", "exsum_release", "exsum_status_string",
+    "ServerConfig", "Server", "exsum_server_default_config", "exsum_server_plan", "exsum_serial_replay",
     "EXPORTED_SYMBOLS",
 ]
 
@@ -29,6 +30,9 @@ EXSUM_OK, EXSUM_EINVAL, EXSUM_ENOMEM, EXSUM_EDEVICE = 0, 1, 2, 3
 EXPORTED_SYMBOLS = [
     "exsum_status_string", "exsum_f64", "exsum_segmented_f64", "exsum_inexact_f64",
     "exsum_get_config", "exsum_set_config", "exsum_f64_cfg", "exsum_release",
+    "exsum_server_default_config", "exsum_server_create", "exsum_server_destroy", "exsum_server_submit",
+    "exsum_server_step", "exsum_server_poll", "exsum_server_drain", "exsum_server_pending",
+    "exsum_server_replay", "exsum_serial_replay", "exsum_server_plan",
 ]
 
 
@@ -50,6 +54,21 @@ class ExsumConfig(ctypes.Structure):
         ("small_grid", ctypes.c_int32),
         ("seg_grid", ctypes.c_int32),
         ("seg_small_max", ctypes.c_int64),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [
+        ("step_terms", ctypes.c_int64),
+        ("piece_terms", ctypes.c_int64),
+        ("short_max", ctypes.c_int64),
+        ("max_slots", ctypes.c_int32),
+        ("max_pieces", ctypes.c_int32),
+        ("max_inflight", ctypes.c_int32),
+        ("precombine", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -87,6 +106,23 @@ def load_library():
         lib.exsum_set_config.restype = I32
         lib.exsum_release.argtypes = []
         lib.exsum_release.restype = I32
+        PCFG = ctypes.POINTER(ServerConfig)
+        PI64 = ctypes.POINTER(ctypes.c_int64)
+        lib.exsum_server_default_config.argtypes = [PCFG]
+        lib.exsum_server_create.argtypes = [PCFG, P, ctypes.POINTER(P)]
+        lib.exsum_server_destroy.argtypes = [P]
+        lib.exsum_server_submit.argtypes = [P, P, I64, P, PI64]
+        lib.exsum_server_step.argtypes = [P, PI64]
+        lib.exsum_server_poll.argtypes = [P, P, I64, PI64]
+        lib.exsum_server_drain.argtypes = [P]
+        lib.exsum_server_pending.argtypes = [P, PI64]
+        lib.exsum_server_replay.argtypes = [P, P, P, P, P, I64, P, P, ctypes.POINTER(ctypes.c_double)]
+        lib.exsum_serial_replay.argtypes = [P, P, P, P, I64, P, P, P, ctypes.POINTER(ctypes.c_double)]
+        lib.exsum_server_plan.argtypes = [PCFG, P, I64, I64, P, P, P, P, P, P, PI64]
+        for name in ("exsum_server_default_config", "exsum_server_create", "exsum_server_destroy",
+                     "exsum_server_submit", "exsum_server_step", "exsum_server_poll", "exsum_server_drain",
+                     "exsum_server_pending", "exsum_server_replay", "exsum_serial_replay", "exsum_server_plan"):
+            getattr(lib, name).restype = I32
         _lib = lib
         return lib
 
@@ -192,3 +228,152 @@ def exsum_set_config(cfg: ExsumConfig) -> None:
 
 def exsum_release() -> None:
     _check(load_library().exsum_release(), "exsum_release")
+
+
+# ---------------------------------------------------------------------------
+# serving loop
+# ---------------------------------------------------------------------------
+
+def _host_array(a, dtype, name):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, ctypes.c_void_p(a.ctypes.data if a.size else 0)
+
+
+def exsum_server_default_config() -> ServerConfig:
+    cfg = ServerConfig()
+    _check(load_library().exsum_server_default_config(ctypes.byref(cfg)), "exsum_server_default_config")
+    return cfg
+
+
+def exsum_server_plan(lens, cfg: ServerConfig = None):
+    """The server's plan for requests of the given lengths, all submitted at
+    once (host only).  Returns a dict of numpy arrays: req, off, len, step,
+    slot, expected (0xFFFFFFFF for pieces of steps that do not complete their
+    request)."""
+    import numpy as np
+    lens, lp = _host_array(lens, np.int64, "lens")
+    lib = load_library()
+    cfgp = ctypes.byref(cfg) if cfg is not None else None
+    count = ctypes.c_int64(0)
+    _check(lib.exsum_server_plan(cfgp, lp, lens.size, 0, None, None, None, None, None, None,
+                                 ctypes.byref(count)), "exsum_server_plan")
+    n = count.value
+    out = {k: np.zeros(n, dtype=t) for k, t in (("req", np.int64), ("off", np.int64), ("len", np.int64),
+                                                   ("step", np.int64), ("slot", np.int32),
+                                                   ("expected", np.uint32))}
+    ptr = {k: ctypes.c_void_p(v.ctypes.data) for k, v in out.items()}
+    _check(lib.exsum_server_plan(cfgp, lp, lens.size, n, ptr["req"], ptr["off"], ptr["len"], ptr["step"],
+                                 ptr["slot"], ptr["expected"], ctypes.byref(count)), "exsum_server_plan")
+    return out
+
+
+class Server:
+    """Continuous-batching exact-sum server on one stream (see exsum.h)."""
+
+    def __init__(self, cfg: ServerConfig = None, stream=None):
+        lib = load_library()
+        self._lib = lib
+        self._h = ctypes.c_void_p(0)
+        self._stream = _stream_handle(stream)
+        cfgp = ctypes.byref(cfg) if cfg is not None else None
+        _check(lib.exsum_server_create(cfgp, self._stream, ctypes.byref(self._h)), "exsum_server_create")
+        self._keep = {}                      # tensors of requests in flight
+
+    def close(self):
+        if self._h:
+            st = self._lib.exsum_server_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+            self._keep.clear()
+            _check(st, "exsum_server_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, x, out, out_index: int = 0) -> int:
+        """Queue the exact sum of the float64 device tensor x into
+        out[out_index]; returns the request id."""
+        x = _dev_f64(x)
+        out = _dev_f64(out, "out")
+        if not 0 <= out_index < out.numel():
+            raise IndexError("out_index out of range")
+        rid = ctypes.c_int64(0)
+        optr = ctypes.c_void_p(out.data_ptr() + 8 * out_index)
+        _check(self._lib.exsum_server_submit(self._h, _ptr(x), x.numel(), optr, ctypes.byref(rid)),
+               "exsum_server_submit")
+        self._keep[rid.value] = (x, out)
+        return rid.value
+
+    def step(self) -> int:
+        n = ctypes.c_int64(0)
+        _check(self._lib.exsum_server_step(self._h, ctypes.byref(n)), "exsum_server_step")
+        return n.value
+
+    def poll(self, max_ids: int = 4096):
+        import numpy as np
+        ids = np.zeros(max_ids, dtype=np.int64)
+        n = ctypes.c_int64(0)
+        _check(self._lib.exsum_server_poll(self._h, ctypes.c_void_p(ids.ctypes.data), max_ids, ctypes.byref(n)),
+               "exsum_server_poll")
+        done = [int(i) for i in ids[:n.value]]
+        for i in done:
+            self._keep.pop(i, None)
+        return done
+
+    def drain(self):
+        _check(self._lib.exsum_server_drain(self._h), "exsum_server_drain")
+
+    def pending(self) -> int:
+        n = ctypes.c_int64(0)
+        _check(self._lib.exsum_server_pending(self._h, ctypes.byref(n)), "exsum_server_pending")
+        return n.value
+
+    def replay(self, pool, starts, lens, arrival_s, out):
+        """Real-time replay of a trace (see exsum_server_replay).  Returns
+        (latency_s numpy array, makespan_s)."""
+        import numpy as np
+        pool = _dev_f64(pool, "pool")
+        out = _dev_f64(out, "out")
+        starts, sp = _host_array(starts, np.int64, "starts")
+        lens, lp = _host_array(lens, np.int64, "lens")
+        arr, ap = _host_array(arrival_s, np.float64, "arrival_s")
+        if not (starts.size == lens.size == arr.size) or out.numel() < lens.size:
+            raise ValueError("trace arrays disagree in length")
+        if lens.size and int((starts + lens).max()) > pool.numel():
+            raise ValueError("a request runs past the end of the pool")
+        lat = np.zeros(lens.size, dtype=np.float64)
+        mk = ctypes.c_double(0.0)
+        _check(self._lib.exsum_server_replay(self._h, _ptr(pool), sp, lp, ap, lens.size, _ptr(out),
+                                             ctypes.c_void_p(lat.ctypes.data), ctypes.byref(mk)),
+               "exsum_server_replay")
+        return lat, mk.value
+
+
+def exsum_serial_replay(pool, starts, lens, arrival_s, out, stream=None):
+    """The same trace served by one exsum_f64 call per request, in arrival
+    order on one stream.  Returns (latency_s, makespan_s)."""
+    import numpy as np
+    pool = _dev_f64(pool, "pool")
+    out = _dev_f64(out, "out")
+    starts, sp = _host_array(starts, np.int64, "starts")
+    lens, lp = _host_array(lens, np.int64, "lens")
+    arr, ap = _host_array(arrival_s, np.float64, "arrival_s")
+    if not (starts.size == lens.size == arr.size) or out.numel() < lens.size:
+        raise ValueError("trace arrays disagree in length")
+    if lens.size and int((starts + lens).max()) > pool.numel():
+        raise ValueError("a request runs past the end of the pool")
+    lat = np.zeros(lens.size, dtype=np.float64)
+    mk = ctypes.c_double(0.0)
+    _check(load_library().exsum_serial_replay(_ptr(pool), sp, lp, ap, lens.size, _ptr(out), _stream_handle(stream),
+                                               ctypes.c_void_p(lat.ctypes.data), ctypes.byref(mk)),
+           "exsum_serial_replay")
+    return lat, mk.value

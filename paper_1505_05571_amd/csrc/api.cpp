@@ -12,6 +12,32 @@
 #include "exsum_internal.h"
 
 namespace exsum {
+
+int status_of(hipError_t e) {
+  if (e == hipSuccess) return EXSUM_OK;
+  (void)hipGetLastError();
+  return e == hipErrorOutOfMemory ? EXSUM_ENOMEM : EXSUM_EDEVICE;
+}
+
+namespace {
+std::mutex g_cu_mu;
+int g_cu[64] = {0};
+}  // namespace
+
+int cu_count(int dev) {
+  if (dev < 0 || dev >= 64) return 256;
+  std::lock_guard<std::mutex> lk(g_cu_mu);
+  if (g_cu[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) {
+      (void)hipGetLastError();
+      v = 256;
+    }
+    g_cu[dev] = v;
+  }
+  return g_cu[dev];
+}
+
 namespace {
 
 std::mutex g_mu;
@@ -33,7 +59,6 @@ exsum_config default_config() {
 }
 
 exsum_config g_cfg = default_config();
-int g_cu[64] = {0};
 
 constexpr int64_t kMaxN = int64_t(1) << 40;
 
@@ -48,24 +73,6 @@ bool config_ok(const exsum_config &c) {
   return true;
 }
 
-int status_of(hipError_t e) {
-  if (e == hipSuccess) return EXSUM_OK;
-  (void)hipGetLastError();
-  return e == hipErrorOutOfMemory ? EXSUM_ENOMEM : EXSUM_EDEVICE;
-}
-
-int cu_count(int dev) {
-  if (dev < 0 || dev >= 64) return 256;
-  if (g_cu[dev] == 0) {
-    int v = 0;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) {
-      (void)hipGetLastError();
-      v = 256;
-    }
-    g_cu[dev] = v;
-  }
-  return g_cu[dev];
-}
 
 // Workspace for (current device, stream); allocated and zeroed on first use.
 int get_workspace(hipStream_t s, Workspace **out, int *dev_out) {

@@ -22,6 +22,11 @@ struct Workspace {
   GlobalAcc *seg_accs = nullptr;
 };
 
+// Host helpers (api.cpp): EXSUM_* status of a HIP error (clearing the HIP
+// error state), and the compute-unit count of a device (cached).
+int status_of(hipError_t e);
+int cu_count(int dev);
+
 // Launchers (kernels_sum.hip).  Return a hipError_t.
 hipError_t launch_large(const double *x, int64_t n, MergeRows *M, double *out, hipStream_t s,
                         int block, int vec, int depth, int mode, int grid, int precombine);
@@ -37,5 +42,25 @@ hipError_t launch_segmented(const double *x, const int64_t *offsets, int64_t nse
                             GlobalAcc *accs, hipStream_t s, int grid, int64_t small_max, int precombine);
 
 size_t merge_rows_bytes();
+
+// One piece of a served request (host and device layout).  `expected` is the
+// request's total number of pieces when this piece belongs to the step that
+// completes the request, kNotFinal otherwise; 1 means "round directly".
+constexpr uint32_t kNotFinal = 0xFFFFFFFFu;
+struct Piece {
+  const double *x;
+  int64_t n;
+  double *out;
+  int32_t slot;
+  uint32_t expected;
+};
+static_assert(sizeof(Piece) == 32, "Piece layout");
+
+// Served pieces (kernels_serve.hip): pieces [0, nshort) have at most
+// short_max terms and are summed one per wavefront; the rest one per
+// workgroup.
+hipError_t launch_pieces(const Piece *pieces, int nshort, int npieces, GlobalAcc *slots, hipStream_t s, int grid,
+                         int precombine);
+int pieces_block();
 
 }  // namespace exsum

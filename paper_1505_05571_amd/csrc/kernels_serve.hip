@@ -1,0 +1,85 @@
+// kernels_serve.hip -- one step of the serving loop: exact sums of a list of
+// pieces of requests (gfx950).
+//
+// A piece is a range of one request's terms.  Pieces [0, nshort) are short
+// and each is summed by one wavefront with the small-superaccumulator body;
+// the others are summed one per workgroup with the large accumulator in
+// carry mode.  A request made of one piece is rounded where it is summed.  A
+// request cut into several pieces (possibly over several steps) adds each
+// piece into its accumulator slot with 64-bit atomics and takes a ticket;
+// pieces of the step that completes the request carry the total piece count,
+// and the piece whose ticket completes the count rounds (Discussion: add the
+// small superaccumulators of the parts, round once).  Steps run in stream
+// order, so every piece of an earlier step has been added before any piece
+// of a later one.
+#include "exsum_blocks.h"
+#include "exsum_internal.h"
+
+namespace exsum {
+namespace {
+
+template <int NW>
+struct PieceShared {
+  LargeShared L;
+  long long wacc[NW][68];
+  unsigned long long wspec[NW][4];
+  unsigned int wD[NW][70];
+};
+
+template <int BLOCK, int VEC, int DEPTH>
+__global__ __launch_bounds__(BLOCK) void piece_kernel(const Piece *__restrict__ P, int nshort, int np,
+                                                      GlobalAcc *__restrict__ slots, int precombine) {
+  constexpr int NW = BLOCK / 64;
+  __shared__ PieceShared<NW> S;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // all lanes active here
+  const int nlong = np - nshort;
+  if (nlong > (int)blockIdx.x) large_init(S.L, tid, BLOCK);
+
+  // short pieces: one per wavefront of the grid (a scalar loop counter)
+  {
+    long long *acc = S.wacc[wave];
+    unsigned long long *spec = S.wspec[wave];
+    unsigned int *D = S.wD[wave];
+    for (int p = (int)blockIdx.x * NW + wave; p < nshort; p += (int)gridDim.x * NW) {
+      const Piece pc = P[p];
+      acc[lane] = 0;
+      if (lane < 4) acc[64 + lane] = 0;
+      if (lane < 3) spec[lane] = 0ull;
+      small_wave_accumulate(acc, spec, pc.x, 0, pc.n, lane);
+      GlobalAcc *g = pc.expected == 1u ? nullptr : &slots[pc.slot];
+      wave_merge_and_round(acc, spec, D, g, pc.expected, pc.out, lane);
+    }
+  }
+  __syncthreads();
+
+  // long pieces: one per workgroup
+  unsigned int tile = 0;
+  for (int p = nshort + (int)blockIdx.x; p < np; p += (int)gridDim.x) {
+    const Piece pc = P[p];
+    accumulate_range<BLOCK, VEC, DEPTH, kCarryMode>(S.L, pc.x, 0, pc.n, precombine, tile);
+    final_flush<BLOCK, true, kCarryMode>(S.L);
+    GlobalAcc *g = pc.expected == 1u ? nullptr : &slots[pc.slot];
+    merge_and_round(S.L.small, S.L.spec, &S.L.ticket, S.L.D, g, pc.expected, pc.out);
+    if (tid < 68) S.L.small[tid] = 0;
+    if (tid < 3) S.L.spec[tid] = 0ull;
+    __syncthreads();
+  }
+}
+
+constexpr int kPieceBlock = 512;
+
+}  // namespace
+
+hipError_t launch_pieces(const Piece *pieces, int nshort, int npieces, GlobalAcc *slots, hipStream_t s, int grid,
+                         int precombine) {
+  if (npieces <= 0) return hipSuccess;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL((piece_kernel<kPieceBlock, 4, 2>), dim3(grid), dim3(kPieceBlock), 0, s, pieces, nshort,
+                     npieces, slots, precombine);
+  return hipGetLastError();
+}
+
+int pieces_block() { return kPieceBlock; }
+
+}  // namespace exsum

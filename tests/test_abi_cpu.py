@@ -78,3 +78,116 @@ def test_config_roundtrip_and_validation(lib):
                 ex.exsum_set_config(c)
     finally:
         ex.exsum_set_config(c0)
+
+
+# ---- serving loop: the scheduler's plan (host only) and host-side checks ----
+
+def plan_invariants(lens, cfg, plan):
+    """Check a plan against the scheduling rules stated in exsum.h."""
+    import numpy as np
+    lens = np.asarray(lens, dtype=np.int64)
+    req, off, ln, st, sl, exp = (plan[k] for k in ("req", "off", "len", "step", "slot", "expected"))
+    NOT_FINAL = 0xFFFFFFFF
+    # every request covered exactly once, in order, in pieces of at most piece_terms
+    for r in range(lens.size):
+        idx = np.nonzero(req == r)[0]
+        assert idx.size >= 1, r
+        assert np.all(np.diff(st[idx]) >= 0)
+        o, l = off[idx], ln[idx]
+        assert o[0] == 0 and np.all(o[1:] == (o + l)[:-1]) and (o + l)[-1] == lens[r], r
+        assert np.all(l <= cfg.piece_terms)
+        last_step = st[idx].max()
+        if lens[r] <= cfg.piece_terms:
+            # never split: one piece, rounded where it is summed, no slot
+            assert idx.size == 1 and exp[idx[0]] == 1 and sl[idx[0]] == -1, r
+        else:
+            assert idx.size >= 2 and np.all(sl[idx] == sl[idx[0]]) and 0 <= sl[idx[0]] < cfg.max_slots
+            fin = st[idx] == last_step
+            assert np.all(exp[idx][fin] == idx.size), r
+            assert np.all(exp[idx][~fin] == NOT_FINAL), r
+    # per step: term budget and piece cap
+    for s in np.unique(st):
+        m = st == s
+        assert ln[m].sum() <= cfg.step_terms
+        assert m.sum() <= cfg.max_pieces
+    # a slot is held by at most one request at a time, and at most max_slots are held
+    spans = {}
+    for r in np.unique(req[sl >= 0]):
+        idx = np.nonzero(req == r)[0]
+        spans[int(r)] = (int(sl[idx[0]]), int(st[idx].min()), int(st[idx].max()))
+    for s in range(int(st.max()) + 1 if st.size else 0):
+        held = [v[0] for v in spans.values() if v[1] <= s <= v[2]]
+        assert len(held) == len(set(held)) and len(held) <= cfg.max_slots
+
+
+def small_cfg(**kw):
+    c = ex.exsum_server_default_config()
+    c.step_terms, c.piece_terms, c.max_slots, c.max_pieces = 1 << 12, 1 << 9, 3, 64
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+def test_server_plan_invariants(lib):
+    import numpy as np
+    rng = np.random.default_rng(0)
+    cases = [
+        [0, 1, 512, 513, 1024, 5000, 0, 3, 100000],
+        list(np.rint(10.0 ** rng.uniform(0, 5.3, size=300)).astype(np.int64)),
+        [1 << 12] * 7 + [1] * 50,
+        [],
+    ]
+    for lens in cases:
+        for cfg in (small_cfg(), small_cfg(max_slots=1, max_pieces=3), small_cfg(step_terms=1 << 9),
+                    ex.exsum_server_default_config()):
+            plan = ex.exsum_server_plan(lens, cfg)
+            plan_invariants(lens, cfg, plan)
+
+
+def test_server_plan_shares_steps_fairly(lib):
+    import numpy as np
+    # a short request behind a long one is served in the first step
+    cfg = small_cfg()
+    plan = ex.exsum_server_plan([1 << 20, 10], cfg)
+    assert plan["step"][plan["req"] == 1][0] == 0
+    # every step of a lone long request uses the whole budget but the last
+    plan = ex.exsum_server_plan([10 * cfg.step_terms + 7], cfg)
+    per_step = np.bincount(plan["step"], weights=plan["len"])
+    assert np.all(per_step[:-1] == cfg.step_terms) and per_step[-1] == 7
+
+
+def test_server_host_side_checks(lib):
+    import ctypes
+    P = ctypes.c_void_p
+    bad = small_cfg(piece_terms=0)
+    h = P(0)
+    assert lib.exsum_server_create(ctypes.byref(bad), None, ctypes.byref(h)) == 1
+    for field, value in (("step_terms", 1), ("max_slots", 0), ("max_inflight", 65), ("max_pieces", 0),
+                         ("short_max", -1), ("precombine", 65)):
+        c = small_cfg(**{field: value})
+        assert lib.exsum_server_create(ctypes.byref(c), None, ctypes.byref(h)) == 1, field
+    assert lib.exsum_server_create(None, None, None) == 1
+    n = ctypes.c_int64(0)
+    assert lib.exsum_server_submit(None, P(8), 1, P(8), ctypes.byref(n)) == 1
+    assert lib.exsum_server_step(None, ctypes.byref(n)) == 1
+    assert lib.exsum_server_poll(None, None, 0, ctypes.byref(n)) == 1
+    assert lib.exsum_server_drain(None) == 1
+    assert lib.exsum_server_destroy(None) == 0
+    d = ctypes.c_double(0)
+    assert lib.exsum_server_replay(None, None, None, None, None, 0, None, None, ctypes.byref(d)) == 1
+    # a trace whose arrivals go backwards, or a negative length, is refused before any device work
+    import numpy as np
+    st = np.zeros(2, dtype=np.int64)
+    ln = np.array([1, -1], dtype=np.int64)
+    ar = np.array([0.0, 1.0])
+    lat = np.zeros(2)
+    args = [P(8), P(st.ctypes.data), P(ln.ctypes.data), P(ar.ctypes.data), 2, P(8), None, P(lat.ctypes.data),
+            ctypes.byref(d)]
+    assert lib.exsum_serial_replay(*args) == 1
+    ln[1] = 1
+    ar[1] = -1.0
+    assert lib.exsum_serial_replay(*args) == 1
+    lens = np.array([-1], dtype=np.int64)
+    cnt = ctypes.c_int64(0)
+    assert lib.exsum_server_plan(None, P(lens.ctypes.data), 1, 0, None, None, None, None, None, None,
+                                 ctypes.byref(cnt)) == 1
