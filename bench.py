@@ -51,6 +51,8 @@ WORKLOADS = {
     "small_normal": "small_normal n=1000 (sign uniform, |N(0,1)| 2^k, k in [-20,20]); latency",
     "segments": "segments nseg=65536 lognormal(median 1000, sigma 2) clipped [1,1e6]; one batched call",
     "copy": "device-to-device copy of 800 MB (reference for HBM bandwidth and counter calibration)",
+    "serve": "served requests: lengths log-uniform [10, 1e8], slices of a resident 1e8-term uniform_exponent pool, "
+             "Poisson arrivals at rho = 0.8 and 2 of the serial service rate",
 }
 
 
@@ -144,6 +146,75 @@ def copy_reference(torch, dev, x, args):
                       "read_plus_write_GBs": round(16.0 * x.size / t / 1e9, 1)}), flush=True)
 
 
+def serve_bench(args):
+    """Continuous-batching server against serial exsum_f64 calls on one
+    trace, replayed in real time at two loads."""
+    import torch
+    import oracle
+    import paper_1505_05571_amd as ex
+    from paper_1505_05571_amd import workloads as W
+    ex.load_library()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    pool = W.uniform_exponent(10 ** 8, seed=0)
+    pt = torch.from_numpy(pool).to(dev)
+    starts, lens, gaps = W.serve_trace(args.serve_requests, seed=1, pool_n=pool.size)
+    nreq = lens.size
+    total_bytes = 8.0 * float(lens.sum())
+    out_serial = torch.empty(nreq, dtype=torch.float64, device=dev)
+    # serial service rate: every request launched at once, back to back
+    ex.exsum_serial_replay(pt, starts[:20], lens[:20], np.zeros(20), out_serial)          # warm-up
+    _, busy = ex.exsum_serial_replay(pt, starts, lens, np.zeros(nreq), out_serial)
+    mean_service = busy / nreq
+    ref = out_serial.cpu().numpy().view(np.uint64).copy()
+    # oracle on a bounded sample of the requests (at most 2e8 terms)
+    rng = np.random.default_rng(2)
+    order = rng.permutation(nreq)
+    pick, budget = [], 2 * 10 ** 8
+    for i in order:
+        if lens[i] <= budget:
+            pick.append(int(i))
+            budget -= int(lens[i])
+    pick = np.array(sorted(pick), dtype=np.int64)
+    want = oracle.sum_ranges_f64(pool, starts[pick], lens[pick])
+    oracle_ok = bool(np.array_equal(ref[pick], want))
+
+    def summary(lat, mk):
+        return {"GBs": round(total_bytes / mk / 1e9, 1), "req_per_s": round(nreq / mk, 1),
+                "makespan_s": round(mk, 4),
+                "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 4),
+                               "p99": round(float(np.percentile(lat, 99)) * 1e3, 4),
+                               "p999": round(float(np.percentile(lat, 99.9)) * 1e3, 4)}}
+
+    loads = {}
+    served_ok = True
+    for rho in (0.8, 2.0):
+        arrival = np.cumsum(gaps) * (mean_service / rho)
+        arrival -= arrival[0]
+        out_b = torch.full((nreq,), np.nan, dtype=torch.float64, device=dev)
+        with ex.Server(stream=torch.cuda.current_stream()) as srv:
+            lat_b, mk_b = srv.replay(pt, starts, lens, arrival, out_b)
+        served_ok &= bool(np.array_equal(out_b.cpu().numpy().view(np.uint64), ref))
+        out_s = torch.full((nreq,), np.nan, dtype=torch.float64, device=dev)
+        lat_s, mk_s = ex.exsum_serial_replay(pt, starts, lens, arrival, out_s)
+        served_ok &= bool(np.array_equal(out_s.cpu().numpy().view(np.uint64), ref))
+        loads["rho_%g" % rho] = {"batched": summary(lat_b, mk_b), "serial": summary(lat_s, mk_s)}
+        print(json.dumps({"progress": "rho %g done" % rho}), file=sys.stderr, flush=True)
+    head = loads["rho_0.8"]["batched"]
+    result = {
+        "metric": "served exact sums: GB/s and p50/p99 request latency (0-ulp)",
+        "value": head["GBs"], "unit": "GB/s", "n_gpus": 1, "steps": nreq, "warmup": 20,
+        "ms_per_step": round(head["makespan_s"] * 1e3 / nreq, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": WORKLOADS["serve"], "requests": nreq, "terms": int(lens.sum()),
+                   "mean_serial_service_ms": round(mean_service * 1e3, 4)},
+        "loads": loads,
+        "parity": {"batched_and_serial_equal": served_ok, "oracle_sample_requests": int(pick.size),
+                   "oracle_sample_equal": oracle_ok},
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -151,6 +222,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="uniform_exponent", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=20000)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -159,6 +231,8 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "serve":
+        return serve_bench(args)
     import torch
     import paper_1505_05571_amd as ex
     ex.load_library()

@@ -75,18 +75,22 @@ int exsum_f64(const double *x, int64_t n, double *out, void *stream);
 
 /*
  * exsum_segmented_f64 -- out[i] = exact sum of x[offsets[i] .. offsets[i+1])
- * for 0 <= i < nseg, all in one persistent launch.
+ * for 0 <= i < nseg.
  *
- * Many independent exact sums (same definition as exsum_f64), one launch.
- * Workgroups take equal shares of the concatenated terms; each piece of a
- * segment takes the small-superaccumulator path (one wavefront) or the
- * large-plus-small path (a workgroup) by its length (Performance
- * evaluations: the small method wins for short sums, the large one for long
- * sums); a segment cut by workgroup boundaries is merged from its pieces.
+ * Many independent exact sums (same definition as exsum_f64) in two
+ * launches on `stream` that write disjoint outputs.  Segments of at most
+ * seg_small_max terms (empty ones included) are summed whole, each by one
+ * wavefront with a small superaccumulator; longer ones by workgroups with
+ * the large superaccumulator, each workgroup taking an equal share of the
+ * concatenated terms, and a segment cut by workgroup boundaries is merged
+ * from its pieces with integer additions (Performance evaluations: the small
+ * method wins for short sums, the large one for long sums; Discussion: parts
+ * summed separately are added as small superaccumulators).
  *   x       : terms, device memory.
  *   offsets : nseg+1 int64 values, device memory, non-decreasing;
  *             offsets[0] need not be 0.  Not checked on the device.
- *   nseg    : number of segments, >= 0.  An empty segment sums to +0.0.
+ *   nseg    : number of segments, 0 <= nseg < 2^31.  An empty segment sums
+ *             to +0.0.
  *   out     : nseg binary64 results, device memory.
  * Nothing is planned on the host and nothing synchronises; after one call on
  * a stream (which allocates that stream's workspace) the call may be
@@ -124,10 +128,11 @@ int exsum_inexact_f64(const double *x, int64_t n, double *out, void *stream);
  *                 added with a single LDS update; 0 disables the pre-combine.
  *   small_max   : inputs with n <= small_max use the small-only kernel.
  *   small_grid  : workgroups of the small-only kernel; 0 = automatic.
- *   seg_grid    : workgroups of the segmented kernel; 0 = one per compute unit.
- *   seg_small_max : segment pieces of at most this many terms are summed by
- *                   one wavefront with the small accumulator alone; longer
- *                   ones by a workgroup with the large accumulator.
+ *   seg_grid    : workgroups of the segmented call's long-segment kernel;
+ *                 0 = one per compute unit.
+ *   seg_small_max : segments of at most this many terms (0 .. 2^20) are
+ *                   summed by one wavefront with the small accumulator
+ *                   alone; longer ones by workgroups with the large one.
  */
 typedef struct {
     int32_t large_block;

@@ -54,7 +54,7 @@ exsum_config default_config() {
   c.small_max = 4096;
   c.small_grid = 0;
   c.seg_grid = 0;
-  c.seg_small_max = 4096;
+  c.seg_small_max = 16384;
   return c;
 }
 
@@ -202,7 +202,12 @@ int exsum_segmented_f64(const double *x, const int64_t *offsets, int64_t nseg, d
     }
     accs = w->seg_accs;
   }
-  return status_of(launch_segmented(x, offsets, nseg, out, accs, s, grid, c.seg_small_max, c.precombine));
+  // short segments: about 24 wavefronts per compute unit, at most one per segment
+  const int64_t per_block = seg_short_waves_per_block();
+  const int64_t waves = std::min<int64_t>(nseg, int64_t(24) * cu_count(dev));
+  const int short_grid = (int)std::max<int64_t>((waves + per_block - 1) / per_block, 1);
+  return status_of(launch_segmented(x, offsets, nseg, out, accs, s, grid, short_grid, c.seg_small_max,
+                                    c.precombine));
 }
 
 int exsum_get_config(exsum_config *cfg) {

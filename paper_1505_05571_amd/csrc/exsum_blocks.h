@@ -149,21 +149,29 @@ __device__ __forceinline__ void add_slot(LargeShared &S, unsigned long long b, b
 }
 
 // Slow tile: re-read this lane's terms (16-byte vectors tb + j*stride for
-// j < nslots, present below `limit`) and add them one slot at a time.  Kept
-// out of line so the hot loop stays small.
+// j < nslots <= kMaxSlots, present below `limit`) and add them one slot at a
+// time.  All loads are issued before the first add, so a tile costs one
+// memory latency.  Kept out of line so the hot loop stays small.
+constexpr int kMaxSlots = 9;
 template <int MODE>
 __device__ __noinline__ void slow_tile(LargeShared *S, const ulonglong2 *__restrict__ xv, long long tb,
                                        long long limit, int stride, int nslots, int precombine, unsigned int tile,
                                        unsigned int thr) {
   const int lane = threadIdx.x & 63;
-#pragma unroll 1
-  for (int j = 0; j < nslots; j++) {
+  ulonglong2 v[kMaxSlots];
+#pragma unroll
+  for (int j = 0; j < kMaxSlots; j++) {
     const long long idx = tb + (long long)j * stride;
-    const bool ok = idx < limit;
-    ulonglong2 v = make_ulonglong2(0ull, 0ull);
-    if (ok) v = xv[idx];
-    add_slot<MODE>(*S, v.x, ok, precombine, tile, lane, thr);
-    add_slot<MODE>(*S, v.y, ok, precombine, tile, lane, thr);
+    v[j] = make_ulonglong2(0ull, 0ull);
+    if (j < nslots && idx < limit) v[j] = xv[idx];
+  }
+#pragma unroll
+  for (int j = 0; j < kMaxSlots; j++) {
+    if (j < nslots) {
+      const bool ok = tb + (long long)j * stride < limit;
+      add_slot<MODE>(*S, v[j].x, ok, precombine, tile, lane, thr);
+      add_slot<MODE>(*S, v[j].y, ok, precombine, tile, lane, thr);
+    }
   }
 }
 
@@ -304,14 +312,11 @@ __device__ __forceinline__ void accumulate_range(LargeShared &S, const double *_
   const long long a = r0 + head;
   const long long nv = (r1 - a) >> 1;
   const bool has_tail = ((r1 - a) & 1) != 0;
-  if (head || has_tail) {
-    unsigned long long b = 0ull;
-    bool valid = false;
-    if (tid == 0 && head) { b = as_bits(x[r0]); valid = true; }
-    if (tid == 1 && has_tail) { b = as_bits(x[r1 - 1]); valid = true; }
-    add_slot<MODE>(S, b, valid, precombine, tile, lane, THR);
-    tile_end<MODE>(S, tile++, tid);
-  }
+  // a misaligned first term and an odd last term: loaded now, added last
+  unsigned long long hb = 0ull;
+  bool hvalid = false;
+  if (tid == 0 && head) { hb = as_bits(x[r0]); hvalid = true; }
+  if (tid == 1 && has_tail) { hb = as_bits(x[r1 - 1]); hvalid = true; }
   const ulonglong2 *__restrict__ xv = reinterpret_cast<const ulonglong2 *>(x + a);
   const long long q = nv / NW;                       // vectors per stream (the last takes the rest)
   const long long ws = (long long)wave * q;
@@ -320,7 +325,7 @@ __device__ __forceinline__ void accumulate_range(LargeShared &S, const double *_
   // Loads are unconditional (an index past the last tile reads the pad tile)
   // so the compiler's wait counts stay exact and a prefetch is never waited
   // for early.
-  static_assert(VEC <= kMaxVec, "pad tile too small");
+  static_assert(VEC <= kMaxVec && VEC + 1 <= kMaxSlots, "pad tile or slow tile too small");
   ulonglong2 buf[DEPTH][VEC];
   auto load = [&](ulonglong2(&bf)[VEC], long long t) {
     const ulonglong2 *tp = (t < ntiles) ? xv + ws + t * TILE_W : g_pad_tile;
@@ -356,6 +361,10 @@ __device__ __forceinline__ void accumulate_range(LargeShared &S, const double *_
   // the last), so at most VEC+1 slots and fewer terms than one full tile
   if (nv > (long long)NW * ntiles * TILE_W) {
     slow_tile<MODE>(&S, xv, ws + ntiles * TILE_W + lane, we, 64, VEC + 1, precombine, tile, THR);
+    tile_end<MODE>(S, tile++, tid);
+  }
+  if (head || has_tail) {
+    add_slot<MODE>(S, hb, hvalid, precombine, tile, lane, THR);
     tile_end<MODE>(S, tile++, tid);
   }
 }
@@ -616,32 +625,121 @@ __device__ __forceinline__ void carry_step(long long *c, int lane) {
   __builtin_amdgcn_wave_barrier();
 }
 
-// Wave adds x[lo .. hi) into acc (68 chunks, zeroed by the caller); specials
-// into spec[3].  Ends with a carry step, so |acc[i]| < 2^33 on return.
-__device__ __forceinline__ void small_wave_accumulate(long long *acc, unsigned long long *spec,
-                                                      const double *__restrict__ x, long long lo, long long hi,
-                                                      int lane) {
-  int steps = 0;
-  for (long long base = lo; base < hi; base += 64) {
-    const long long i = base + lane;
+// The small-accumulator body of one wavefront.  The wave's accumulator is
+// COPIES copies of 68 chunks (small_acc_words<COPIES>() words in LDS); lane l
+// adds into copy l % COPIES, so the 64 lanes' adds to one chunk land on
+// several addresses instead of one (same-address LDS atomics serialise,
+// which binds when many wavefronts share a compute unit).  The copies sit
+// 544 bytes apart, on different banks.
+template <int COPIES>
+constexpr int small_acc_words() { return 68 * COPIES; }
+
+// Zero a wave's accumulator copies and side words.
+template <int COPIES>
+__device__ __forceinline__ void small_wave_zero(long long *acc, unsigned long long *spec, int lane) {
+  constexpr int kWords = small_acc_words<COPIES>();
+#pragma unroll
+  for (int k = 0; k < (kWords + 63) / 64; k++) {
+    const int i = lane + 64 * k;
+    if (i < kWords) acc[i] = 0;
+  }
+  if (lane < 3) spec[lane] = 0ull;
+}
+
+// Each lane takes kSmallU terms per batch (term base + 64 j + lane); two
+// batches of registers alternate, so the next batch's loads are in flight
+// while the current one is added.  Load indices are clamped to the last
+// term, so every load is issued unconditionally and the compiler's wait
+// counts stay exact; clamped lanes add nothing.
+constexpr int kSmallU = 8;
+__device__ __forceinline__ void small_batch_load(unsigned long long (&b)[kSmallU], const double *__restrict__ x,
+                                                 long long base, long long last, int lane) {
+#pragma unroll
+  for (int j = 0; j < kSmallU; j++) {
+    long long i = base + (long long)j * 64 + lane;
+    i = i < last ? i : last;
+    b[j] = as_bits(x[i]);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+}
+__device__ __forceinline__ void small_batch_add(long long *mine, unsigned long long *spec,
+                                                const unsigned long long (&b)[kSmallU], long long base, long long hi,
+                                                int lane) {
+#pragma unroll
+  for (int j = 0; j < kSmallU; j++) {
+    const long long i = base + (long long)j * 64 + lane;
     if (i < hi) {
-      const unsigned long long b = as_bits(x[i]);
-      if (is_special(b)) {
-        note_special(b, &spec[0], &spec[1], &spec[2]);
+      if (is_special(b[j])) {
+        note_special(b[j], &spec[0], &spec[1], &spec[2]);
       } else {
         int h;
         long long plo, phi;
-        term_pieces(b, h, plo, phi);
-        atomicAdd((unsigned long long *)&acc[h], (unsigned long long)plo);
-        atomicAdd((unsigned long long *)&acc[h + 1], (unsigned long long)phi);
+        term_pieces(b[j], h, plo, phi);
+        atomicAdd((unsigned long long *)&mine[h], (unsigned long long)plo);
+        atomicAdd((unsigned long long *)&mine[h + 1], (unsigned long long)phi);
       }
     }
-    if (++steps == 31) {
-      steps = 0;
-      carry_step(acc, lane);
+  }
+}
+template <int COPIES>
+__device__ __forceinline__ void small_carry_all(long long *acc, int lane) {
+#pragma unroll
+  for (int c = 0; c < COPIES; c++) carry_step(acc + 68 * c, lane);
+}
+
+// Wave adds x[lo .. hi) into acc (small_acc_words<COPIES>() words, zeroed by
+// the caller); specials into spec[3].  On return the sum is in the first 68
+// words, each below COPIES * 2^33 in magnitude.
+template <int COPIES>
+__device__ __forceinline__ void small_wave_accumulate(long long *acc, unsigned long long *spec,
+                                                      const double *__restrict__ x, long long lo, long long hi,
+                                                      int lane) {
+  // a copy's chunk receives at most 64 / COPIES pieces below 2^52 per
+  // 64-term step; a carry step after every kEvery batches keeps it below
+  // 1536 * 2^52 < 2^63
+  constexpr int kEvery = 3 * COPIES;
+  static_assert(64 % COPIES == 0 && kEvery * kSmallU * (64 / COPIES) <= 1536, "carry interval");
+  long long *mine = acc + 68 * (lane % COPIES);
+  if (hi > lo) {
+    constexpr long long kB = 64 * kSmallU;
+    const long long last = hi - 1;
+    unsigned long long A[kSmallU], B[kSmallU];
+    small_batch_load(A, x, lo, last, lane);
+    int batches = 0;
+    for (long long base = lo;;) {
+      small_batch_load(B, x, base + kB, last, lane);
+      small_batch_add(mine, spec, A, base, hi, lane);
+      base += kB;
+      if (++batches == kEvery) {
+        batches = 0;
+        small_carry_all<COPIES>(acc, lane);
+      }
+      if (base >= hi) break;
+      small_batch_load(A, x, base + kB, last, lane);
+      small_batch_add(mine, spec, B, base, hi, lane);
+      base += kB;
+      if (++batches == kEvery) {
+        batches = 0;
+        small_carry_all<COPIES>(acc, lane);
+      }
+      if (base >= hi) break;
     }
   }
-  carry_step(acc, lane);
+  small_carry_all<COPIES>(acc, lane);
+  if (COPIES > 1) {
+    // add the copies into the first: every copy is below 2^33 after its carry
+    __builtin_amdgcn_wave_barrier();
+    long long t0 = 0, t1 = 0;
+#pragma unroll
+    for (int c = 0; c < COPIES; c++) {
+      t0 += acc[68 * c + lane];
+      if (lane < 4) t1 += acc[68 * c + 64 + lane];
+    }
+    __builtin_amdgcn_wave_barrier();
+    acc[lane] = t0;
+    if (lane < 4) acc[64 + lane] = t1;
+    __builtin_amdgcn_wave_barrier();
+  }
 }
 
 }  // namespace exsum

@@ -38,8 +38,12 @@ hipError_t launch_inexact(const double *x, int64_t n, double *partials, unsigned
 
 // Segmented sums (kernels_seg.hip).
 size_t global_acc_bytes();
+// Two launches: short segments (at most small_max terms) by `short_grid`
+// blocks of wavefronts, long ones by `grid` workgroups.
 hipError_t launch_segmented(const double *x, const int64_t *offsets, int64_t nseg, double *out,
-                            GlobalAcc *accs, hipStream_t s, int grid, int64_t small_max, int precombine);
+                            GlobalAcc *accs, hipStream_t s, int grid, int short_grid, int64_t small_max,
+                            int precombine);
+int seg_short_waves_per_block();
 
 size_t merge_rows_bytes();
 

@@ -18,10 +18,12 @@
 namespace exsum {
 namespace {
 
+constexpr int kPieceCopies = 8;
+
 template <int NW>
 struct PieceShared {
   LargeShared L;
-  long long wacc[NW][68];
+  long long wacc[NW][small_acc_words<kPieceCopies>()];
   unsigned long long wspec[NW][4];
   unsigned int wD[NW][70];
 };
@@ -43,10 +45,8 @@ __global__ __launch_bounds__(BLOCK) void piece_kernel(const Piece *__restrict__ 
     unsigned int *D = S.wD[wave];
     for (int p = (int)blockIdx.x * NW + wave; p < nshort; p += (int)gridDim.x * NW) {
       const Piece pc = P[p];
-      acc[lane] = 0;
-      if (lane < 4) acc[64 + lane] = 0;
-      if (lane < 3) spec[lane] = 0ull;
-      small_wave_accumulate(acc, spec, pc.x, 0, pc.n, lane);
+      small_wave_zero<kPieceCopies>(acc, spec, lane);
+      small_wave_accumulate<kPieceCopies>(acc, spec, pc.x, 0, pc.n, lane);
       GlobalAcc *g = pc.expected == 1u ? nullptr : &slots[pc.slot];
       wave_merge_and_round(acc, spec, D, g, pc.expected, pc.out, lane);
     }

@@ -39,20 +39,20 @@ template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void small_kernel(const double *__restrict__ x, long long n,
                                                       MergeRows *__restrict__ M, double *__restrict__ out) {
   constexpr int NW = BLOCK / 64;
-  __shared__ long long s_acc[NW][68];
+  __shared__ long long s_acc[NW][small_acc_words<1>()];
   __shared__ long long s_tot[68];
   __shared__ unsigned long long s_spec[3];
   __shared__ unsigned int s_flag[2];
   __shared__ unsigned int s_D[70];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int i = tid; i < NW * 68; i += BLOCK) (&s_acc[0][0])[i] = 0;
+  for (int i = tid; i < NW * small_acc_words<1>(); i += BLOCK) (&s_acc[0][0])[i] = 0;
   if (tid < 3) s_spec[tid] = 0ull;
   __syncthreads();
   const long long G = gridDim.x;
   const long long r0 = n * (long long)blockIdx.x / G, r1 = n * (long long)(blockIdx.x + 1) / G;
   const long long len = r1 - r0;
   const long long w0 = r0 + len * wave / NW, w1 = r0 + len * (wave + 1) / NW;
-  small_wave_accumulate(s_acc[wave], s_spec, x, w0, w1, lane);
+  small_wave_accumulate<1>(s_acc[wave], s_spec, x, w0, w1, lane);
   __syncthreads();
   if (tid < 68) {
     long long t = 0;
