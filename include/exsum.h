@@ -123,9 +123,12 @@ int exsum_inexact_f64(const double *x, int64_t n, double *out, void *stream);
  *                 (256,2,4,0) (512,3,2,0) (512,2,2,0) (256,4,3,1) (512,4,2,1)
  *                 (512,2,4,1) (1024,2,2,1) (1024,4,2,1).
  *   large_grid  : workgroups of the large kernel; 0 = one per compute unit.
- *   precombine  : lanes of a wavefront that must share one (sign, exponent)
- *                 chunk before they are first summed across the wavefront and
- *                 added with a single LDS update; 0 disables the pre-combine.
+ *   precombine  : pre-combine across a wavefront: a tile whose terms all
+ *                 share one (sign, exponent) chunk is summed across the
+ *                 wavefront and added with a single LDS update, and on the
+ *                 rare slow path (tiles with infinities or NaNs, leftovers)
+ *                 this many lanes sharing a chunk are summed first; 0
+ *                 disables both.
  *   small_max   : inputs with n <= small_max use the small-only kernel.
  *   small_grid  : workgroups of the small-only kernel; 0 = automatic.
  *   seg_grid    : workgroups of the segmented call's long-segment kernel;

@@ -45,7 +45,7 @@ std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
 
 exsum_config default_config() {
   exsum_config c;
-  c.large_block = 512;
+  c.large_block = 1024;
   c.large_vec = 4;
   c.large_depth = 2;
   c.large_mode = 1;

@@ -177,12 +177,15 @@ __device__ __noinline__ void slow_tile(LargeShared *S, const ulonglong2 *__restr
 
 // Fast tile: the NT terms every lane holds are all present.  Returns false,
 // having changed nothing, when the tile needs the slow path (an infinity or
-// NaN somewhere, or a chunk shared by many lanes but not by the whole tile).
+// NaN somewhere).
 //   * whole wave, whole tile in one chunk: each lane sums its NT values, the
-//     wave sums those, one lane adds the total (64*NT terms) to the chunk;
+//     wave sums those, one lane adds the total (64*NT terms) to the chunk
+//     (64 same-address adds per instruction would bind the LDS);
 //   * otherwise one 64-bit LDS add per term (plus a count add in count
 //     mode), all issued before any returned value is examined; the rare
 //     threshold crossings or carries are found with one ballot per term.
+//     Lanes that share a chunk partly serialise their adds, which costs far
+//     less than taking the tile through the slow path.
 template <int NT, int MODE>
 __device__ __forceinline__ bool fast_tile(LargeShared &S, const unsigned long long (&b)[NT], int precombine,
                                           unsigned int tile, int lane, unsigned int thr) {
@@ -208,7 +211,6 @@ __device__ __forceinline__ bool fast_tile(LargeShared &S, const unsigned long lo
       if (lane == 0) chunk_add<MODE>(S, leader, s, 64u * NT, tile, thr);
       return true;
     }
-    if (__popcll(__ballot(key[0] == leader)) >= precombine) return false;
   }
   if (MODE == kCountMode) {
     unsigned int old[NT];
