@@ -163,6 +163,58 @@ int exsum_f64_cfg(const double *x, int64_t n, double *out, void *stream,
 int exsum_release(void);
 
 /* ------------------------------------------------------------------------
+ * Further exact reductions over the same path (same conventions, argument
+ * checks and asynchrony as exsum_f64; `n` counts terms or pairs, and the
+ * launch uses the small-only kernel for n <= small_max, else the large
+ * kernel in its default variant).
+ * ------------------------------------------------------------------------ */
+
+/* out[0] = sum of x[i]*x[i], each product first rounded to binary64 by the
+   IEEE multiply, then summed exactly and rounded once (the squared norm of
+   the Performance evaluations). */
+int exsum_sqnorm_f64(const double *x, int64_t n, double *out, void *stream);
+
+/* out[0] = sum of x[i]*y[i], each product first rounded to binary64, then
+   summed exactly and rounded once (the paper's dot product).  x and y need
+   not share an alignment.  A NaN product's bits are those the device's IEEE
+   multiply gives (the sign is ignored, as for any NaN term). */
+int exsum_dot_f64(const double *x, const double *y, int64_t n, double *out, void *stream);
+
+/* out[0] = (exact sum of x[0..n)) / n, rounded once to binary64, ties to
+   even (Discussion: a mean that is correctly rounded).  n == 0 gives +0, as
+   does a mean that rounds to zero. */
+int exsum_mean_f64(const double *x, int64_t n, double *out, void *stream);
+
+/* out[0] = the exact sum of the binary32 terms x[0..n), rounded once to
+   binary32 (the single-precision variant of the Introduction).  Terms are
+   converted exactly; a NaN result carries the largest binary32 NaN payload
+   with the quiet bit set; +Inf with -Inf gives 0x7FC00000; an exact zero
+   gives +0.  x and out are float device pointers. */
+int exsum_f32(const float *x, int64_t n, float *out, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Streaming, mergeable accumulator (Discussion: parts of a sum are summed
+ * separately and their small superaccumulators added).  The state is
+ * EXSUM_ACC_BYTES of caller-owned device memory, 64-byte aligned: 67
+ * signed 64-bit chunks of the small superaccumulator (chunk i weighs
+ * 2^(32i-1075), kept below 2^33 in magnitude after every update), a pad
+ * word, the +Inf and -Inf flags, the largest NaN pattern, and padding.
+ * Updates on one stream are ordered; updates of one state from different
+ * streams must be ordered by the caller.  Rounding reads the state and does
+ * not change it, so a running sum can be read at any time.
+ * ------------------------------------------------------------------------ */
+#define EXSUM_ACC_BYTES 576
+
+/* Set the state to the empty sum. */
+int exsum_acc_zero(void *acc, void *stream);
+/* Add the exact sum of x[0..n) (not rounded). */
+int exsum_acc_add_f64(void *acc, const double *x, int64_t n, void *stream);
+/* dst += src (two different states). */
+int exsum_acc_merge(void *dst, const void *src, void *stream);
+/* out[0] = the state's value rounded once to binary64 (as exsum_f64). */
+int exsum_acc_round_f64(const void *acc, double *out, void *stream);
+
+/* ------------------------------------------------------------------------
  * Serving loop: many independent exact sums (requests) arriving over time,
  * served by continuous batching on one stream.
  *

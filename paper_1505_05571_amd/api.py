@@ -16,6 +16,7 @@ __all__ = [
     "exsum_f64", "exsum_segmented_f64", "exsum_inexact_f64", "exsum_f64_cfg",
     "exsum_get_config", "exsum_set_config", "exsum_release", "exsum_status_string",
     "ServerConfig", "Server", "exsum_server_default_config", "exsum_server_plan", "exsum_serial_replay",
+    "exsum_sqnorm_f64", "exsum_dot_f64", "exsum_mean_f64", "exsum_f32", "Accumulator", "EXSUM_ACC_BYTES",
     "EXPORTED_SYMBOLS",
 ]
 
@@ -33,7 +34,11 @@ EXPORTED_SYMBOLS = [
     "exsum_server_default_config", "exsum_server_create", "exsum_server_destroy", "exsum_server_submit",
     "exsum_server_step", "exsum_server_poll", "exsum_server_drain", "exsum_server_pending",
     "exsum_server_replay", "exsum_serial_replay", "exsum_server_plan",
+    "exsum_sqnorm_f64", "exsum_dot_f64", "exsum_mean_f64", "exsum_f32",
+    "exsum_acc_zero", "exsum_acc_add_f64", "exsum_acc_merge", "exsum_acc_round_f64",
 ]
+
+EXSUM_ACC_BYTES = 576
 
 
 class ExsumError(RuntimeError):
@@ -119,6 +124,17 @@ def load_library():
         lib.exsum_server_replay.argtypes = [P, P, P, P, P, I64, P, P, ctypes.POINTER(ctypes.c_double)]
         lib.exsum_serial_replay.argtypes = [P, P, P, P, I64, P, P, P, ctypes.POINTER(ctypes.c_double)]
         lib.exsum_server_plan.argtypes = [PCFG, P, I64, I64, P, P, P, P, P, P, PI64]
+        lib.exsum_sqnorm_f64.argtypes = [P, I64, P, P]
+        lib.exsum_dot_f64.argtypes = [P, P, I64, P, P]
+        lib.exsum_mean_f64.argtypes = [P, I64, P, P]
+        lib.exsum_f32.argtypes = [P, I64, P, P]
+        lib.exsum_acc_zero.argtypes = [P, P]
+        lib.exsum_acc_add_f64.argtypes = [P, P, I64, P]
+        lib.exsum_acc_merge.argtypes = [P, P, P]
+        lib.exsum_acc_round_f64.argtypes = [P, P, P]
+        for name in ("exsum_sqnorm_f64", "exsum_dot_f64", "exsum_mean_f64", "exsum_f32", "exsum_acc_zero",
+                     "exsum_acc_add_f64", "exsum_acc_merge", "exsum_acc_round_f64"):
+            getattr(lib, name).restype = I32
         for name in ("exsum_server_default_config", "exsum_server_create", "exsum_server_destroy",
                      "exsum_server_submit", "exsum_server_step", "exsum_server_poll", "exsum_server_drain",
                      "exsum_server_pending", "exsum_server_replay", "exsum_serial_replay", "exsum_server_plan"):
@@ -214,6 +230,96 @@ def exsum_segmented_f64(x, offsets, out=None, stream=None):
     _check(load_library().exsum_segmented_f64(_ptr(x), _ptr(offsets), nseg, _ptr(out),
                                                _stream_handle(stream)), "exsum_segmented_f64")
     return out
+
+
+def _dev_f32(x, name="x"):
+    import torch
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError("%s must be a device (HIP) tensor" % name)
+    if x.dtype != torch.float32:
+        raise TypeError("%s must be float32" % name)
+    if not x.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return x
+
+
+def exsum_sqnorm_f64(x, out=None, stream=None):
+    """Exact sum of x[i]*x[i] (products rounded to binary64), rounded once."""
+    x = _dev_f64(x)
+    out = _out1(x, out)
+    _check(load_library().exsum_sqnorm_f64(_ptr(x), x.numel(), _ptr(out), _stream_handle(stream)),
+           "exsum_sqnorm_f64")
+    return out
+
+
+def exsum_dot_f64(x, y, out=None, stream=None):
+    """Exact sum of x[i]*y[i] (products rounded to binary64), rounded once."""
+    x = _dev_f64(x)
+    y = _dev_f64(y, "y")
+    if y.numel() != x.numel():
+        raise ValueError("x and y differ in length")
+    out = _out1(x, out)
+    _check(load_library().exsum_dot_f64(_ptr(x), _ptr(y), x.numel(), _ptr(out), _stream_handle(stream)),
+           "exsum_dot_f64")
+    return out
+
+
+def exsum_mean_f64(x, out=None, stream=None):
+    """Exact sum of x divided by its length, rounded once (n = 0 gives +0)."""
+    x = _dev_f64(x)
+    out = _out1(x, out)
+    _check(load_library().exsum_mean_f64(_ptr(x), x.numel(), _ptr(out), _stream_handle(stream)),
+           "exsum_mean_f64")
+    return out
+
+
+def exsum_f32(x, out=None, stream=None):
+    """Exact sum of a float32 device tensor, rounded once to binary32."""
+    import torch
+    x = _dev_f32(x)
+    if out is None:
+        out = torch.empty(1, dtype=torch.float32, device=x.device)
+    out = _dev_f32(out, "out")
+    _check(load_library().exsum_f32(_ptr(x), x.numel(), _ptr(out), _stream_handle(stream)), "exsum_f32")
+    return out
+
+
+class Accumulator:
+    """A device-resident exact accumulator (EXSUM_ACC_BYTES of device memory):
+    add terms in any number of calls, merge accumulators, round at any time."""
+
+    def __init__(self, device="cuda:0", stream=None):
+        import torch
+        self.state = torch.empty(EXSUM_ACC_BYTES // 8, dtype=torch.int64, device=device)
+        self._stream = stream
+        self.zero()
+
+    def _h(self):
+        return ctypes.c_void_p(self.state.data_ptr())
+
+    def zero(self):
+        _check(load_library().exsum_acc_zero(self._h(), _stream_handle(self._stream)), "exsum_acc_zero")
+        return self
+
+    def add(self, x):
+        x = _dev_f64(x)
+        _check(load_library().exsum_acc_add_f64(self._h(), _ptr(x), x.numel(), _stream_handle(self._stream)),
+               "exsum_acc_add_f64")
+        return self
+
+    def merge(self, other: "Accumulator"):
+        _check(load_library().exsum_acc_merge(self._h(), other._h(), _stream_handle(self._stream)),
+               "exsum_acc_merge")
+        return self
+
+    def round(self, out=None):
+        import torch
+        if out is None:
+            out = torch.empty(1, dtype=torch.float64, device=self.state.device)
+        out = _dev_f64(out, "out")
+        _check(load_library().exsum_acc_round_f64(self._h(), _ptr(out), _stream_handle(self._stream)),
+               "exsum_acc_round_f64")
+        return out
 
 
 def exsum_get_config() -> ExsumConfig:

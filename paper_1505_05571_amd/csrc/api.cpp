@@ -128,6 +128,39 @@ int run_sum(const double *x, int64_t n, double *out, hipStream_t s, const exsum_
   return status_of(e);
 }
 
+// Launch shape of a sum over the small-only kernel or the large kernel's
+// default variant (op_block() threads, 4 positions per thread per tile, T
+// terms per position).
+struct OpPlan {
+  bool small;
+  int grid;
+};
+OpPlan plan_op(int64_t n, int64_t terms_per_position, const exsum_config &c, int dev) {
+  OpPlan p;
+  p.small = n <= c.small_max;
+  if (p.small) {
+    p.grid = c.small_grid ? c.small_grid : (int)std::min<int64_t>(std::max<int64_t>((n + 8191) / 8192, 1), 64);
+  } else if (c.large_grid) {
+    p.grid = c.large_grid;
+  } else {
+    const int64_t tile_terms = terms_per_position * op_block() * 4;
+    const int64_t want = (n + 4 * tile_terms - 1) / (4 * tile_terms);
+    p.grid = (int)std::min<int64_t>(std::max<int64_t>(want, 1), int64_t(cu_count(dev)));
+  }
+  return p;
+}
+
+// Common set-up of the entry points below: configuration, workspace.
+int op_setup(hipStream_t s, exsum_config *c, Workspace **w, int *dev) {
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    *c = g_cfg;
+  }
+  return get_workspace(s, w, dev);
+}
+
+bool acc_ptr_ok(const void *acc) { return acc != nullptr && (reinterpret_cast<uintptr_t>(acc) & 63) == 0; }
+
 }  // namespace
 }  // namespace exsum
 
@@ -208,6 +241,83 @@ int exsum_segmented_f64(const double *x, const int64_t *offsets, int64_t nseg, d
   const int short_grid = (int)std::max<int64_t>((waves + per_block - 1) / per_block, 1);
   return status_of(launch_segmented(x, offsets, nseg, out, accs, s, grid, short_grid, c.seg_small_max,
                                     c.precombine));
+}
+
+int exsum_sqnorm_f64(const double *x, int64_t n, double *out, void *stream) {
+  if (n < 0 || n >= kMaxN || out == nullptr || (n > 0 && x == nullptr)) return EXSUM_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  exsum_config c;
+  Workspace *w = nullptr;
+  int dev = 0;
+  int st = op_setup(s, &c, &w, &dev);
+  if (st != EXSUM_OK) return st;
+  const OpPlan p = plan_op(n, 2, c, dev);
+  return status_of(launch_sqnorm(x, n, out, w->rows, s, p.grid, p.small, c.precombine));
+}
+
+int exsum_dot_f64(const double *x, const double *y, int64_t n, double *out, void *stream) {
+  if (n < 0 || n >= kMaxN || out == nullptr || (n > 0 && (x == nullptr || y == nullptr))) return EXSUM_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  exsum_config c;
+  Workspace *w = nullptr;
+  int dev = 0;
+  int st = op_setup(s, &c, &w, &dev);
+  if (st != EXSUM_OK) return st;
+  const OpPlan p = plan_op(n, 2, c, dev);
+  return status_of(launch_dot(x, y, n, out, w->rows, s, p.grid, p.small, c.precombine));
+}
+
+int exsum_mean_f64(const double *x, int64_t n, double *out, void *stream) {
+  if (n < 0 || n >= kMaxN || out == nullptr || (n > 0 && x == nullptr)) return EXSUM_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  exsum_config c;
+  Workspace *w = nullptr;
+  int dev = 0;
+  int st = op_setup(s, &c, &w, &dev);
+  if (st != EXSUM_OK) return st;
+  const OpPlan p = plan_op(n, 2, c, dev);
+  return status_of(launch_mean(x, n, out, w->rows, s, p.grid, p.small, c.precombine));
+}
+
+int exsum_f32(const float *x, int64_t n, float *out, void *stream) {
+  if (n < 0 || n >= kMaxN || out == nullptr || (n > 0 && x == nullptr)) return EXSUM_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  exsum_config c;
+  Workspace *w = nullptr;
+  int dev = 0;
+  int st = op_setup(s, &c, &w, &dev);
+  if (st != EXSUM_OK) return st;
+  const OpPlan p = plan_op(n, 4, c, dev);
+  return status_of(launch_f32(x, n, out, w->rows, s, p.grid, p.small, c.precombine));
+}
+
+int exsum_acc_zero(void *acc, void *stream) {
+  if (!acc_ptr_ok(acc)) return EXSUM_EINVAL;
+  return status_of(launch_acc_zero(static_cast<GlobalAcc *>(acc), static_cast<hipStream_t>(stream)));
+}
+
+int exsum_acc_add_f64(void *acc, const double *x, int64_t n, void *stream) {
+  if (!acc_ptr_ok(acc) || n < 0 || n >= kMaxN || (n > 0 && x == nullptr)) return EXSUM_EINVAL;
+  if (n == 0) return EXSUM_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  exsum_config c;
+  Workspace *w = nullptr;
+  int dev = 0;
+  int st = op_setup(s, &c, &w, &dev);
+  if (st != EXSUM_OK) return st;
+  const OpPlan p = plan_op(n, 2, c, dev);
+  return status_of(launch_acc_add(x, n, static_cast<GlobalAcc *>(acc), w->rows, s, p.grid, p.small, c.precombine));
+}
+
+int exsum_acc_merge(void *dst, const void *src, void *stream) {
+  if (!acc_ptr_ok(dst) || !acc_ptr_ok(src) || dst == src) return EXSUM_EINVAL;
+  return status_of(launch_acc_merge(static_cast<GlobalAcc *>(dst), static_cast<const GlobalAcc *>(src),
+                                    static_cast<hipStream_t>(stream)));
+}
+
+int exsum_acc_round_f64(const void *acc, double *out, void *stream) {
+  if (!acc_ptr_ok(acc) || out == nullptr) return EXSUM_EINVAL;
+  return status_of(launch_acc_round(static_cast<const GlobalAcc *>(acc), out, static_cast<hipStream_t>(stream)));
 }
 
 int exsum_get_config(exsum_config *cfg) {

@@ -148,29 +148,33 @@ __device__ __forceinline__ void add_slot(LargeShared &S, unsigned long long b, b
   if (key != kNone) chunk_add<MODE>(S, key, val, 1u, tile, thr);
 }
 
-// Slow tile: re-read this lane's terms (16-byte vectors tb + j*stride for
-// j < nslots <= kMaxSlots, present below `limit`) and add them one slot at a
-// time.  All loads are issued before the first add, so a tile costs one
-// memory latency.  Kept out of line so the hot loop stays small.
+// Slow tile: re-read this lane's vector positions (tb + j*stride for
+// j < nslots <= kMaxSlots, present below `limit`, counted from the aligned
+// term a) and add their terms one slot at a time.  All loads are issued
+// before the first add, so a tile costs one memory latency.  Kept out of line
+// so the hot loop stays small.
 constexpr int kMaxSlots = 9;
-template <int MODE>
-__device__ __noinline__ void slow_tile(LargeShared *S, const ulonglong2 *__restrict__ xv, long long tb,
-                                       long long limit, int stride, int nslots, int precombine, unsigned int tile,
-                                       unsigned int thr) {
+template <int MODE, class Src>
+__device__ __noinline__ void slow_tile(LargeShared *S, Src src, long long a, long long tb, long long limit,
+                                       int stride, int nslots, int precombine, unsigned int tile, unsigned int thr) {
+  constexpr int T = Src::kTPV;
   const int lane = threadIdx.x & 63;
-  ulonglong2 v[kMaxSlots];
+  const typename Src::Ptr base = src.at(a, 0);
+  typename Src::Vec v[kMaxSlots];
 #pragma unroll
   for (int j = 0; j < kMaxSlots; j++) {
     const long long idx = tb + (long long)j * stride;
-    v[j] = make_ulonglong2(0ull, 0ull);
-    if (j < nslots && idx < limit) v[j] = xv[idx];
+    v[j] = Src::zero();
+    if (j < nslots && idx < limit) v[j] = Src::load_plain(base, idx);
   }
 #pragma unroll
   for (int j = 0; j < kMaxSlots; j++) {
     if (j < nslots) {
       const bool ok = tb + (long long)j * stride < limit;
-      add_slot<MODE>(*S, v[j].x, ok, precombine, tile, lane, thr);
-      add_slot<MODE>(*S, v[j].y, ok, precombine, tile, lane, thr);
+      unsigned long long t[T];
+      src.terms(v[j], t);
+#pragma unroll
+      for (int k = 0; k < T; k++) add_slot<MODE>(*S, t[k], ok, precombine, tile, lane, thr);
     }
   }
 }
@@ -278,7 +282,7 @@ __device__ __forceinline__ void tile_end(LargeShared &S, unsigned int tile, int 
   }
 }
 
-// 16-byte streaming load that does not displace cached data (the input is
+// 16-byte streaming loads that do not displace cached data (the input is
 // read exactly once).
 typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ ulonglong2 stream_load(const ulonglong2 *p) {
@@ -293,34 +297,191 @@ __device__ __forceinline__ ulonglong2 stream_load(const ulonglong2 *p) {
 constexpr int kMaxVec = 8;
 static __device__ ulonglong2 g_pad_tile[64 * kMaxVec];
 
-// Add x[r0 .. r1) into the workgroup's large accumulator.  A misaligned first
-// term and an odd last term are added as scalars.  The 16-byte vectors are
-// split into one contiguous stream per wavefront; a wave's tile is 64*VEC
-// vectors (each load instruction covers 1 KiB), with the next DEPTH tiles'
+// ---------------------------------------------------------------------------
+// Term sources.  A source yields the terms to sum as binary64 bit patterns:
+//   kTPV               terms per vector position (one 16-byte load of the
+//                      primary input);
+//   head_terms(r0)     terms before the first 16-byte-aligned position;
+//   at(a, v), pad()    where vector position v (counted from the aligned
+//                      term a) and the pad tile are; load(p, k) a
+//                      non-temporal load of position k from there,
+//                      load_plain(p, k) an ordinary one, zero() empty
+//                      registers;
+//   terms(V, t)        the kTPV patterns of loaded registers;
+//   sload(i), sterm(R) the raw load of scalar term i and its pattern.
+// Loads and transforms are separate, so a transform (a product, a format
+// conversion) never forces an early wait on a prefetch.
+// ---------------------------------------------------------------------------
+
+// binary64 terms.
+struct SrcF64 {
+  const double *x;
+  static constexpr int kTPV = 2;
+  typedef const ulonglong2 *Ptr;
+  typedef ulonglong2 Vec;
+  typedef unsigned long long Raw;
+  __device__ long long head_terms(long long r0) const {
+    return (reinterpret_cast<uintptr_t>(x + r0) & 15) ? 1 : 0;
+  }
+  __device__ Ptr at(long long a, long long v) const { return reinterpret_cast<Ptr>(x + a) + v; }
+  __device__ static Ptr pad() { return g_pad_tile; }
+  __device__ static Vec load(Ptr p, long long k) { return stream_load(p + k); }
+  __device__ static Vec load_plain(Ptr p, long long k) { return p[k]; }
+  __device__ static Vec zero() { return make_ulonglong2(0ull, 0ull); }
+  __device__ void terms(const Vec &v, unsigned long long (&t)[2]) const {
+    t[0] = v.x;
+    t[1] = v.y;
+  }
+  __device__ Raw sload(long long i) const { return as_bits(x[i]); }
+  __device__ unsigned long long sterm(Raw r) const { return r; }
+};
+
+// Products x[i]*x[i], each rounded to binary64 by the IEEE multiply (the
+// paper's squared norm, Performance evaluations).
+struct SrcSq : SrcF64 {
+  __device__ static unsigned long long sq(unsigned long long b) {
+    const double v = __longlong_as_double((long long)b);
+    return as_bits(v * v);
+  }
+  __device__ void terms(const Vec &v, unsigned long long (&t)[2]) const {
+    t[0] = sq(v.x);
+    t[1] = sq(v.y);
+  }
+  __device__ unsigned long long sterm(Raw r) const { return sq(r); }
+};
+
+// Products x[i]*y[i], each rounded to binary64 (the paper's dot product).
+// YA: y + a is 16-byte aligned whenever x + a is; otherwise y is read with
+// two 8-byte loads per position.
+template <bool YA>
+struct SrcDot {
+  const double *x;
+  const double *y;
+  static constexpr int kTPV = 2;
+  struct Ptr {
+    const ulonglong2 *p;
+    const double *q;
+  };
+  struct Vec {
+    ulonglong2 a, b;
+  };
+  struct Raw {
+    unsigned long long a, b;
+  };
+  __device__ static unsigned long long mul(unsigned long long u, unsigned long long v) {
+    return as_bits(__longlong_as_double((long long)u) * __longlong_as_double((long long)v));
+  }
+  __device__ long long head_terms(long long r0) const {
+    return (reinterpret_cast<uintptr_t>(x + r0) & 15) ? 1 : 0;
+  }
+  __device__ Ptr at(long long a, long long v) const {
+    return Ptr{reinterpret_cast<const ulonglong2 *>(x + a) + v, y + a + 2 * v};
+  }
+  __device__ static Ptr pad() { return Ptr{g_pad_tile, reinterpret_cast<const double *>(g_pad_tile)}; }
+  __device__ static Vec load(Ptr p, long long k) {
+    Vec r;
+    r.a = stream_load(p.p + k);
+    if (YA) {
+      r.b = stream_load(reinterpret_cast<const ulonglong2 *>(p.q) + k);
+    } else {
+      r.b.x = (unsigned long long)__builtin_nontemporal_load(reinterpret_cast<const long long *>(p.q) + 2 * k);
+      r.b.y = (unsigned long long)__builtin_nontemporal_load(reinterpret_cast<const long long *>(p.q) + 2 * k + 1);
+    }
+    return r;
+  }
+  __device__ static Vec load_plain(Ptr p, long long k) {
+    Vec r;
+    r.a = p.p[k];
+    r.b.x = as_bits(p.q[2 * k]);
+    r.b.y = as_bits(p.q[2 * k + 1]);
+    return r;
+  }
+  __device__ static Vec zero() { return Vec{make_ulonglong2(0ull, 0ull), make_ulonglong2(0ull, 0ull)}; }
+  __device__ void terms(const Vec &v, unsigned long long (&t)[2]) const {
+    t[0] = mul(v.a.x, v.b.x);
+    t[1] = mul(v.a.y, v.b.y);
+  }
+  __device__ Raw sload(long long i) const { return Raw{as_bits(x[i]), as_bits(y[i])}; }
+  __device__ unsigned long long sterm(Raw r) const { return mul(r.a, r.b); }
+};
+
+// binary32 terms, converted exactly to binary64 patterns with integer
+// operations (every binary32 value is a binary64 value; Formats).  NaN
+// payloads move up by 29 bits, so the largest binary64 NaN pattern maps back
+// to the largest binary32 one.
+__device__ __forceinline__ unsigned long long f32_to_f64_bits(unsigned int b) {
+  const unsigned long long s = (unsigned long long)(b >> 31) << 63;
+  const unsigned int e = (b >> 23) & 255u, m = b & 0x7FFFFFu;
+  if (e == 255u) return s | (0x7FFull << 52) | ((unsigned long long)m << 29);
+  if (e != 0u) return s | ((unsigned long long)(e + 896u) << 52) | ((unsigned long long)m << 29);
+  if (m == 0u) return s;
+  const int p = 31 - __clz(m);                       // leading bit of a denormal, 0..22
+  return s | ((unsigned long long)(p + 874) << 52) | (((unsigned long long)m << (52 - p)) & ((1ull << 52) - 1));
+}
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+struct SrcF32 {
+  const float *x;
+  static constexpr int kTPV = 4;
+  typedef const uint4 *Ptr;
+  typedef uint4 Vec;
+  typedef unsigned int Raw;
+  __device__ long long head_terms(long long r0) const {
+    return (long long)(((16u - (unsigned int)(reinterpret_cast<uintptr_t>(x + r0) & 15)) & 15u) >> 2);
+  }
+  __device__ Ptr at(long long a, long long v) const { return reinterpret_cast<Ptr>(x + a) + v; }
+  __device__ static Ptr pad() { return reinterpret_cast<Ptr>(g_pad_tile); }
+  __device__ static Vec load(Ptr p, long long k) {
+    const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p + k));
+    return make_uint4(v.x, v.y, v.z, v.w);
+  }
+  __device__ static Vec load_plain(Ptr p, long long k) { return p[k]; }
+  __device__ static Vec zero() { return make_uint4(0u, 0u, 0u, 0u); }
+  __device__ void terms(const Vec &v, unsigned long long (&t)[4]) const {
+    t[0] = f32_to_f64_bits(v.x);
+    t[1] = f32_to_f64_bits(v.y);
+    t[2] = f32_to_f64_bits(v.z);
+    t[3] = f32_to_f64_bits(v.w);
+  }
+  __device__ Raw sload(long long i) const { return __float_as_uint(x[i]); }
+  __device__ unsigned long long sterm(Raw r) const { return f32_to_f64_bits(r); }
+};
+
+// Add the source's terms r0 .. r1 into the workgroup's large accumulator.
+// Terms before the first 16-byte-aligned position and after the last whole
+// one are added as scalars.  The vector positions are split into one
+// contiguous stream per wavefront; a wave's tile is 64*VEC positions (each
+// load instruction covers 1 KiB per input), with the next DEPTH tiles'
 // loads in flight in a ring of register buffers.  Every wave runs the same
 // number of full tiles (count mode puts a workgroup barrier after each); the
-// leftover vectors of each stream form one last, partial tile.
-template <int BLOCK, int VEC, int DEPTH, int MODE>
-__device__ __forceinline__ void accumulate_range(LargeShared &S, const double *__restrict__ x, long long r0,
-                                                 long long r1, int precombine, unsigned int &tile) {
+// leftover positions of each stream form one last, partial tile.
+template <int BLOCK, int VEC, int DEPTH, int MODE, class Src>
+__device__ __forceinline__ void accumulate_range(LargeShared &S, const Src &src, long long r0, long long r1,
+                                                 int precombine, unsigned int &tile) {
+  constexpr int T = Src::kTPV;
   constexpr int NW = BLOCK / 64;
-  constexpr int TILE_W = 64 * VEC;            // vectors per wave per tile
-  constexpr int TILE_V = BLOCK * VEC;         // vectors per workgroup per tile
-  static_assert(MODE != kCountMode || 2 * TILE_V < kCap, "tile too large for the count bound");
-  constexpr unsigned int THR = (MODE == kCountMode) ? (unsigned int)(kCap - 2 * TILE_V) : 0u;
+  constexpr int TILE_W = 64 * VEC;            // positions per wave per tile
+  constexpr int TILE_V = BLOCK * VEC;         // positions per workgroup per tile
+  static_assert(MODE != kCountMode || T * TILE_V < kCap, "tile too large for the count bound");
+  constexpr unsigned int THR = (MODE == kCountMode) ? (unsigned int)(kCap - T * TILE_V) : 0u;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (r1 <= r0) return;
-  const long long head = (reinterpret_cast<uintptr_t>(x + r0) & 15) ? 1 : 0;
+  long long head = src.head_terms(r0);
+  if (head > r1 - r0) head = r1 - r0;
   const long long a = r0 + head;
-  const long long nv = (r1 - a) >> 1;
-  const bool has_tail = ((r1 - a) & 1) != 0;
-  // a misaligned first term and an odd last term: loaded now, added last
-  unsigned long long hb = 0ull;
+  const long long nv = (r1 - a) / T;
+  const long long tail = (r1 - a) - nv * T;
+  // scalar terms (at most 2(T-1), on the first lanes of wave 0): loaded now,
+  // added last
+  typename Src::Raw hr{};
   bool hvalid = false;
-  if (tid == 0 && head) { hb = as_bits(x[r0]); hvalid = true; }
-  if (tid == 1 && has_tail) { hb = as_bits(x[r1 - 1]); hvalid = true; }
-  const ulonglong2 *__restrict__ xv = reinterpret_cast<const ulonglong2 *>(x + a);
-  const long long q = nv / NW;                       // vectors per stream (the last takes the rest)
+  if (tid < head) {
+    hr = src.sload(r0 + tid);
+    hvalid = true;
+  } else if (tid < head + tail) {
+    hr = src.sload(r1 - tail + (tid - head));
+    hvalid = true;
+  }
+  const long long q = nv / NW;                       // positions per stream (the last takes the rest)
   const long long ws = (long long)wave * q;
   const long long we = (wave == NW - 1) ? nv : ws + q;
   const long long ntiles = q / TILE_W;               // full tiles, the same for every wave
@@ -328,24 +489,26 @@ __device__ __forceinline__ void accumulate_range(LargeShared &S, const double *_
   // so the compiler's wait counts stay exact and a prefetch is never waited
   // for early.
   static_assert(VEC <= kMaxVec && VEC + 1 <= kMaxSlots, "pad tile or slow tile too small");
-  ulonglong2 buf[DEPTH][VEC];
-  auto load = [&](ulonglong2(&bf)[VEC], long long t) {
-    const ulonglong2 *tp = (t < ntiles) ? xv + ws + t * TILE_W : g_pad_tile;
+  typename Src::Vec buf[DEPTH][VEC];
+  auto load = [&](typename Src::Vec(&bf)[VEC], long long t) {
+    const typename Src::Ptr tp = (t < ntiles) ? src.at(a, ws + t * TILE_W) : Src::pad();
 #pragma unroll
-    for (int j = 0; j < VEC; j++) bf[j] = stream_load(&tp[lane + j * 64]);
+    for (int j = 0; j < VEC; j++) bf[j] = Src::load(tp, lane + j * 64);
     // keep the scheduler from hoisting work on other buffers above these
     // loads (which would force an early wait on them)
     __builtin_amdgcn_sched_barrier(0);
   };
-  auto process = [&](const ulonglong2(&bf)[VEC], long long t) {
-    unsigned long long b[2 * VEC];
+  auto process = [&](const typename Src::Vec(&bf)[VEC], long long t) {
+    unsigned long long b[T * VEC];
 #pragma unroll
     for (int j = 0; j < VEC; j++) {
-      b[2 * j] = bf[j].x;
-      b[2 * j + 1] = bf[j].y;
+      unsigned long long u[T];
+      src.terms(bf[j], u);
+#pragma unroll
+      for (int k = 0; k < T; k++) b[T * j + k] = u[k];
     }
-    if (!fast_tile<2 * VEC, MODE>(S, b, precombine, tile, lane, THR))
-      slow_tile<MODE>(&S, xv, ws + t * TILE_W + lane, we, 64, VEC, precombine, tile, THR);
+    if (!fast_tile<T * VEC, MODE>(S, b, precombine, tile, lane, THR))
+      slow_tile<MODE, Src>(&S, src, a, ws + t * TILE_W + lane, we, 64, VEC, precombine, tile, THR);
     tile_end<MODE>(S, tile++, tid);
   };
   if (ntiles > 0) {
@@ -359,14 +522,14 @@ __device__ __forceinline__ void accumulate_range(LargeShared &S, const double *_
       }
     }
   }
-  // leftover: fewer than TILE_W vectors per stream (plus up to NW-1 more in
-  // the last), so at most VEC+1 slots and fewer terms than one full tile
+  // leftover: fewer than TILE_W positions per stream (plus up to NW-1 more
+  // in the last), so at most VEC+1 slots and fewer terms than one full tile
   if (nv > (long long)NW * ntiles * TILE_W) {
-    slow_tile<MODE>(&S, xv, ws + ntiles * TILE_W + lane, we, 64, VEC + 1, precombine, tile, THR);
+    slow_tile<MODE, Src>(&S, src, a, ws + ntiles * TILE_W + lane, we, 64, VEC + 1, precombine, tile, THR);
     tile_end<MODE>(S, tile++, tid);
   }
-  if (head || has_tail) {
-    add_slot<MODE>(S, hb, hvalid, precombine, tile, lane, THR);
+  if (head || tail) {
+    add_slot<MODE>(S, hvalid ? src.sterm(hr) : 0ull, hvalid, precombine, tile, lane, THR);
     tile_end<MODE>(S, tile++, tid);
   }
 }
@@ -448,7 +611,7 @@ __device__ __forceinline__ bool merge_and_round(long long *s_small, unsigned lon
   __syncthreads();
   if (expected <= 1) {
     if (tid < 64) {
-      const unsigned long long r = round_chunks_wave(s_small, spec[0], spec[1], spec[2], s_D, tid);
+      const unsigned long long r = round_chunks_wave<FmtF64>(s_small, spec[0], spec[1], spec[2], s_D, tid);
       if (tid == 0) out[0] = __longlong_as_double((long long)r);
     }
     __syncthreads();
@@ -477,7 +640,7 @@ __device__ __forceinline__ bool merge_and_round(long long *s_small, unsigned lon
   if (tid == 99) atomicExch(&g->ticket, 0u);
   __syncthreads();
   if (tid < 64) {
-    const unsigned long long r = round_chunks_wave(s_small, spec[0], spec[1], spec[2], s_D, tid);
+    const unsigned long long r = round_chunks_wave<FmtF64>(s_small, spec[0], spec[1], spec[2], s_D, tid);
     if (tid == 0) out[0] = __longlong_as_double((long long)r);
   }
   __syncthreads();
@@ -516,7 +679,7 @@ __device__ __forceinline__ void wave_merge_and_round(long long *acc, unsigned lo
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   }
-  const unsigned long long r = round_chunks_wave(acc, spec[0], spec[1], spec[2], D, lane);
+  const unsigned long long r = round_chunks_wave<FmtF64>(acc, spec[0], spec[1], spec[2], D, lane);
   if (lane == 0) out[0] = __longlong_as_double((long long)r);
 }
 
@@ -524,8 +687,9 @@ __device__ __forceinline__ void wave_merge_and_round(long long *acc, unsigned lo
 // grid takes part, so a shared accumulator would see heavy atomic
 // contention).  Each workgroup stores its small accumulator as a row; groups
 // of kMergeGroup rows are summed by the group's last arrival and the group
-// sums by the last group.  Returns true in the workgroup that wrote *out.
-// Called by every thread (block of at least 128 threads).
+// sums by the last group, which applies the finisher to the total.  Returns
+// true in that workgroup.  Called by every thread (block of at least 128
+// threads).
 // Combine word w of rows [r0, r0+nr) of a row array: chunk words add, the
 // infinity flags OR, the NaN word takes the unsigned maximum.  Sixteen loads
 // are in flight at a time.
@@ -554,17 +718,15 @@ __device__ __forceinline__ long long combine_rows(const long long (*rows)[kRowWo
   return combine_rows_kind<2>(rows, r0, nr, w);
 }
 
-__device__ __forceinline__ bool merge_rows_and_round(long long *s_small, unsigned long long *spec,
-                                                     unsigned int *s_flag, unsigned int *s_D,
-                                                     MergeRows *__restrict__ M, double *__restrict__ out) {
+template <class Fin>
+__device__ __forceinline__ bool merge_rows_and_finish(long long *s_small, unsigned long long *spec,
+                                                      unsigned int *s_flag, unsigned int *s_D,
+                                                      MergeRows *__restrict__ M, const Fin &fin) {
   const int tid = threadIdx.x;
   const unsigned int G = gridDim.x, b = blockIdx.x;
   __syncthreads();
   if (G == 1) {
-    if (tid < 64) {
-      const unsigned long long r = round_chunks_wave(s_small, spec[0], spec[1], spec[2], s_D, tid);
-      if (tid == 0) out[0] = __longlong_as_double((long long)r);
-    }
+    fin(s_small, spec, s_D);
     __syncthreads();
     return true;
   }
@@ -593,10 +755,7 @@ __device__ __forceinline__ bool merge_rows_and_round(long long *s_small, unsigne
   }
   if (tid == 0) __hip_atomic_store(&M->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
-  if (tid < 64) {
-      const unsigned long long r = round_chunks_wave(s_small, spec[0], spec[1], spec[2], s_D, tid);
-      if (tid == 0) out[0] = __longlong_as_double((long long)r);
-    }
+  fin(s_small, spec, s_D);
   __syncthreads();
   return true;
 }
@@ -654,29 +813,32 @@ __device__ __forceinline__ void small_wave_zero(long long *acc, unsigned long lo
 // term, so every load is issued unconditionally and the compiler's wait
 // counts stay exact; clamped lanes add nothing.
 constexpr int kSmallU = 8;
-__device__ __forceinline__ void small_batch_load(unsigned long long (&b)[kSmallU], const double *__restrict__ x,
-                                                 long long base, long long last, int lane) {
+template <class Src>
+__device__ __forceinline__ void small_batch_load(typename Src::Raw (&b)[kSmallU], const Src &src, long long base,
+                                                 long long last, int lane) {
 #pragma unroll
   for (int j = 0; j < kSmallU; j++) {
     long long i = base + (long long)j * 64 + lane;
     i = i < last ? i : last;
-    b[j] = as_bits(x[i]);
+    b[j] = src.sload(i);
   }
   __builtin_amdgcn_sched_barrier(0);
 }
-__device__ __forceinline__ void small_batch_add(long long *mine, unsigned long long *spec,
-                                                const unsigned long long (&b)[kSmallU], long long base, long long hi,
+template <class Src>
+__device__ __forceinline__ void small_batch_add(long long *mine, unsigned long long *spec, const Src &src,
+                                                const typename Src::Raw (&b)[kSmallU], long long base, long long hi,
                                                 int lane) {
 #pragma unroll
   for (int j = 0; j < kSmallU; j++) {
     const long long i = base + (long long)j * 64 + lane;
     if (i < hi) {
-      if (is_special(b[j])) {
-        note_special(b[j], &spec[0], &spec[1], &spec[2]);
+      const unsigned long long t = src.sterm(b[j]);
+      if (is_special(t)) {
+        note_special(t, &spec[0], &spec[1], &spec[2]);
       } else {
         int h;
         long long plo, phi;
-        term_pieces(b[j], h, plo, phi);
+        term_pieces(t, h, plo, phi);
         atomicAdd((unsigned long long *)&mine[h], (unsigned long long)plo);
         atomicAdd((unsigned long long *)&mine[h + 1], (unsigned long long)phi);
       }
@@ -689,13 +851,12 @@ __device__ __forceinline__ void small_carry_all(long long *acc, int lane) {
   for (int c = 0; c < COPIES; c++) carry_step(acc + 68 * c, lane);
 }
 
-// Wave adds x[lo .. hi) into acc (small_acc_words<COPIES>() words, zeroed by
-// the caller); specials into spec[3].  On return the sum is in the first 68
+// Wave adds the source's terms lo .. hi into acc (small_acc_words<COPIES>()
+// words, zeroed by the caller); specials into spec[3].  On return the sum is in the first 68
 // words, each below COPIES * 2^33 in magnitude.
-template <int COPIES>
-__device__ __forceinline__ void small_wave_accumulate(long long *acc, unsigned long long *spec,
-                                                      const double *__restrict__ x, long long lo, long long hi,
-                                                      int lane) {
+template <int COPIES, class Src>
+__device__ __forceinline__ void small_wave_accumulate(long long *acc, unsigned long long *spec, const Src &src,
+                                                      long long lo, long long hi, int lane) {
   // a copy's chunk receives at most 64 / COPIES pieces below 2^52 per
   // 64-term step; a carry step after every kEvery batches keeps it below
   // 1536 * 2^52 < 2^63
@@ -705,20 +866,20 @@ __device__ __forceinline__ void small_wave_accumulate(long long *acc, unsigned l
   if (hi > lo) {
     constexpr long long kB = 64 * kSmallU;
     const long long last = hi - 1;
-    unsigned long long A[kSmallU], B[kSmallU];
-    small_batch_load(A, x, lo, last, lane);
+    typename Src::Raw A[kSmallU], B[kSmallU];
+    small_batch_load(A, src, lo, last, lane);
     int batches = 0;
     for (long long base = lo;;) {
-      small_batch_load(B, x, base + kB, last, lane);
-      small_batch_add(mine, spec, A, base, hi, lane);
+      small_batch_load(B, src, base + kB, last, lane);
+      small_batch_add(mine, spec, src, A, base, hi, lane);
       base += kB;
       if (++batches == kEvery) {
         batches = 0;
         small_carry_all<COPIES>(acc, lane);
       }
       if (base >= hi) break;
-      small_batch_load(A, x, base + kB, last, lane);
-      small_batch_add(mine, spec, B, base, hi, lane);
+      small_batch_load(A, src, base + kB, last, lane);
+      small_batch_add(mine, spec, src, B, base, hi, lane);
       base += kB;
       if (++batches == kEvery) {
         batches = 0;
@@ -743,5 +904,70 @@ __device__ __forceinline__ void small_wave_accumulate(long long *acc, unsigned l
     __builtin_amdgcn_wave_barrier();
   }
 }
+
+// ---------------------------------------------------------------------------
+// Finishers: what the workgroup holding the merged small accumulator does
+// with it.  Called by every thread of that workgroup; c is 68 chunks in LDS
+// (|c[i]| < 2^62), spec the 3 side words, D 70 words of LDS scratch.
+// ---------------------------------------------------------------------------
+
+// Round to binary64 (Small: obtaining the correctly rounded result).
+struct FinF64 {
+  double *out;
+  __device__ void operator()(long long *c, unsigned long long *spec, unsigned int *D) const {
+    const int tid = threadIdx.x;
+    if (tid < 64) {
+      const unsigned long long r = round_chunks_wave<FmtF64>(c, spec[0], spec[1], spec[2], D, tid);
+      if (tid == 0) out[0] = __longlong_as_double((long long)r);
+    }
+  }
+};
+
+// Round to binary32 (the single-precision variant named in the
+// Introduction).
+struct FinF32 {
+  float *out;
+  __device__ void operator()(long long *c, unsigned long long *spec, unsigned int *D) const {
+    const int tid = threadIdx.x;
+    if (tid < 64) {
+      const unsigned long long r = round_chunks_wave<FmtF32>(c, spec[0], spec[1], spec[2], D, tid);
+      if (tid == 0) out[0] = __uint_as_float((unsigned int)r);
+    }
+  }
+};
+
+// The exact sum divided by n, rounded once (Discussion); n = 0 gives +0.
+struct FinMean {
+  double *out;
+  unsigned long long n;
+  __device__ void operator()(long long *c, unsigned long long *spec, unsigned int *D) const {
+    if (threadIdx.x == 0) {
+      const unsigned long long r = n ? round_mean_f64(c, spec[0], spec[1], spec[2], D, n) : 0ull;
+      out[0] = __longlong_as_double((long long)r);
+    }
+  }
+};
+
+// Add into a caller-owned accumulator (the mergeable state of the streaming
+// interface): acc += c with integer additions, one parallel carry step to
+// keep every chunk below 2^33, infinity flags ORed, the NaN word maximised
+// (Discussion: small superaccumulators of parts are added).  The stream
+// orders the calls that touch one accumulator, so plain accesses suffice.
+struct FinAcc {
+  GlobalAcc *acc;
+  __device__ void operator()(long long *c, unsigned long long *spec, unsigned int *) const {
+    const int tid = threadIdx.x;
+    if (tid < 68) c[tid] += (long long)acc->chunk[tid];
+    __syncthreads();
+    if (tid < 64) carry_step(c, tid);
+    __syncthreads();
+    if (tid < 68) acc->chunk[tid] = (unsigned long long)c[tid];
+    if (tid == 0) {
+      acc->pos_inf |= spec[0];
+      acc->neg_inf |= spec[1];
+      if (spec[2] > acc->nan_bits) acc->nan_bits = spec[2];
+    }
+  }
+};
 
 }  // namespace exsum

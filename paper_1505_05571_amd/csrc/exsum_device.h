@@ -174,21 +174,57 @@ __device__ __forceinline__ void note_special(unsigned long long b, unsigned long
   }
 }
 
-// ---- carry propagation and rounding (one thread, on a private copy) --------
+// ---- target formats of the final rounding --------------------------------
+//
+// A sum is held as X = sum c[i] 2^(32i) in units of 2^-1075 (half the
+// smallest binary64 denormal).  A format with P significand bits (hidden bit
+// included) whose smallest denormal is 2^U units rounds X at shift
+// sh = max(bitlen(X) - P, U): q = the P bits from sh up, then round to
+// nearest, ties to even, on the bits below.  The result's magnitude bits are
+// ((sh - U) << (P - 1)) + q: a normal q carries its hidden bit into the
+// exponent field, a denormal q (sh == U) has exponent field 0, and a rounding
+// overflow (q == 2^P) moves into the exponent field by itself.  Exponent
+// field EMAX means overflow to infinity (Small: rounding; Formats).
+struct FmtF64 {
+  static constexpr int P = 53;
+  static constexpr int U = 1;
+  static constexpr unsigned long long EMAX = 2047;
+  static constexpr int SIGN = 63;
+};
+struct FmtF32 {
+  static constexpr int P = 24;
+  static constexpr int U = 926;      // 2^-149 = 2^926 * 2^-1075
+  static constexpr unsigned long long EMAX = 255;
+  static constexpr int SIGN = 31;
+};
 
-// Round the value sum c[i] 2^(32i-1075) (i < 67, any int64 chunks whose
-// partial sums stay in range) to binary64 bits, round to nearest, ties to
-// even.  Specials take precedence.  Serial code, run by a single lane; D is
-// caller-provided scratch of 70 words (LDS, so no private memory is used).
-__device__ inline unsigned long long round_chunks(const long long *c, unsigned long long pos_inf,
-                                                  unsigned long long neg_inf, unsigned long long nan_bits,
-                                                  unsigned int *D) {
-  if (nan_bits) return nan_bits | (1ull << 51);
-  if (pos_inf && neg_inf) return 0x7FF8000000000000ull;
-  if (pos_inf) return 0x7FF0000000000000ull;
-  if (neg_inf) return 0xFFF0000000000000ull;
+// Result bits when an infinity or NaN was seen (*has = true), else 0.  Terms
+// are binary64 bit patterns (binary32 inputs are converted exactly), so
+// nan_bits is the largest binary64 (bits & ~sign) over the NaN terms; for a
+// binary32 result it maps back to the largest binary32 payload.
+template <class F>
+__device__ __forceinline__ unsigned long long special_result(unsigned long long pos_inf, unsigned long long neg_inf,
+                                                             unsigned long long nan_bits, bool *has) {
+  constexpr unsigned long long kInf = F::EMAX << (F::P - 1);
+  constexpr unsigned long long kQuiet = 1ull << (F::P - 2);
+  *has = true;
+  if (nan_bits) {
+    if (F::P == 53) return nan_bits | kQuiet;
+    return kInf | ((nan_bits >> 29) & ((1ull << 23) - 1)) | kQuiet;
+  }
+  if (pos_inf && neg_inf) return kInf | kQuiet;
+  if (pos_inf) return kInf;
+  if (neg_inf) return (1ull << F::SIGN) | kInf;
+  *has = false;
+  return 0;
+}
 
-  // carry propagation: digits 0..65 into [0, 2^32), the rest into the top
+// ---- carry propagation and rounding (one thread) ---------------------------
+
+// Magnitude digits of sum c[i] 2^(32i) (i < 67, int64 chunks whose partial
+// sums stay in range): D[0..66] in [0, 2^32), D[67..69] = 0; returns the
+// sign (1 negative).  Serial, one lane; D is 70 words of scratch in LDS.
+__device__ inline int magnitude_digits(const long long *c, unsigned int *D) {
   long long carry = 0;
   for (int i = 0; i < 66; i++) {
     const long long v = c[i] + carry;
@@ -198,37 +234,103 @@ __device__ inline unsigned long long round_chunks(const long long *c, unsigned l
   long long top = c[66] + carry;                      // |top| < 2^31 for any real input
   D[66] = (unsigned int)top;
   D[67] = D[68] = D[69] = 0;
-  unsigned long long sign = 0;
-  if (top < 0) {                                      // magnitude by two's-complement negation
-    sign = 1ull << 63;
-    unsigned long long cy = 1;
-    for (int i = 0; i < 67; i++) {
-      const unsigned long long t = (unsigned long long)(unsigned int)~D[i] + cy;
-      D[i] = (unsigned int)t;
-      cy = t >> 32;
-    }
+  if (top >= 0) return 0;
+  unsigned long long cy = 1;                          // magnitude by two's-complement negation
+  for (int i = 0; i < 67; i++) {
+    const unsigned long long t = (unsigned long long)(unsigned int)~D[i] + cy;
+    D[i] = (unsigned int)t;
+    cy = t >> 32;
   }
+  return 1;
+}
+
+// Round the value sum c[i] 2^(32i-1075) to format F, round to nearest, ties
+// to even (Small: obtaining the correctly rounded result); specials take
+// precedence; an exact zero gives +0.  Serial code, run by a single lane.
+template <class F>
+__device__ inline unsigned long long round_chunks(const long long *c, unsigned long long pos_inf,
+                                                  unsigned long long neg_inf, unsigned long long nan_bits,
+                                                  unsigned int *D) {
+  bool has;
+  const unsigned long long sp = special_result<F>(pos_inf, neg_inf, nan_bits, &has);
+  if (has) return sp;
+  const unsigned long long sign = (unsigned long long)magnitude_digits(c, D) << F::SIGN;
   int t = 66;
   while (t >= 0 && D[t] == 0) t--;
   if (t < 0) return 0;                                // exact zero -> +0.0
-  // X = sum D[i] 2^(32i) in units of 2^-1075 (X is even)
-  const int B = 32 * t + 32 - __builtin_clz(D[t]);   // bit length of X
-  if (B <= 53) {                                      // denormal (or smallest normal after none)
-    const unsigned long long X = (unsigned long long)D[0] | ((unsigned long long)D[1] << 32);
-    return sign | (X >> 1);
-  }
-  const int sh = B - 53;                              // >= 1
+  const int Bl = 32 * t + 32 - __builtin_clz(D[t]);  // bit length of X
+  int sh = Bl - F::P;
+  if (sh < F::U) sh = F::U;
   const int w = sh >> 5, o = sh & 31;
   unsigned long long q = ((unsigned long long)D[w] | ((unsigned long long)D[w + 1] << 32)) >> o;
   if (o) q |= (unsigned long long)D[w + 2] << (64 - o);
-  q &= (1ull << 53) - 1;
-  const int rpos = sh - 1;                            // round bit position
+  q &= (1ull << F::P) - 1;
+  const int rpos = sh - 1;                            // round bit position (>= 0)
   const unsigned int rbit = (D[rpos >> 5] >> (rpos & 31)) & 1u;
   unsigned int sticky = D[rpos >> 5] & ((1u << (rpos & 31)) - 1u);
   for (int i = 0; i < (rpos >> 5); i++) sticky |= D[i];
-  unsigned long long E = (unsigned long long)sh;      // biased exponent
   if (rbit && (sticky || (q & 1))) q += 1;
-  if (q == (1ull << 53)) { q = 1ull << 52; E += 1; }
+  unsigned long long bits = ((unsigned long long)(sh - F::U) << (F::P - 1)) + q;
+  if ((bits >> (F::P - 1)) >= F::EMAX) bits = F::EMAX << (F::P - 1);
+  return sign | bits;
+}
+
+// The exact mean: the value sum c[i] 2^(32i-1075) divided by n >= 1, rounded
+// once to binary64 (Discussion, on a correctly rounded mean).  With A the
+// magnitude in units of 2^-1074 (X/2; X is even), Q = floor(A/n) and
+// R = A mod n: a quotient below 2^53 rounds on R alone, a longer one on its
+// bit below the 53 kept and the sticky OR of the bits further down and R.
+// A mean that rounds to zero is +0.  Serial, one lane; D is 70 words of LDS.
+__device__ inline unsigned long long round_mean_f64(const long long *c, unsigned long long pos_inf,
+                                                    unsigned long long neg_inf, unsigned long long nan_bits,
+                                                    unsigned int *D, unsigned long long n) {
+  bool has;
+  const unsigned long long sp = special_result<FmtF64>(pos_inf, neg_inf, nan_bits, &has);
+  if (has) return sp;
+  const unsigned long long sign = (unsigned long long)magnitude_digits(c, D) << 63;
+  // A = X / 2, then Q = A / n in place, 16 bits at a time (r < n < 2^48)
+  for (int i = 0; i < 67; i++) D[i] = (D[i] >> 1) | (D[i + 1] << 31);
+  unsigned long long r = 0;
+  for (int i = 66; i >= 0; i--) {
+    const unsigned int d = D[i];
+    r = (r << 16) | (d >> 16);
+    const unsigned long long qh = r / n;
+    r -= qh * n;
+    r = (r << 16) | (d & 0xFFFFu);
+    const unsigned long long ql = r / n;
+    r -= ql * n;
+    D[i] = (unsigned int)((qh << 16) | ql);
+  }
+  int t = 66;
+  while (t >= 0 && D[t] == 0) t--;
+  const int b = (t < 0) ? 0 : 32 * t + 32 - __builtin_clz(D[t]);
+  unsigned long long q;
+  int sh;
+  bool up;
+  if (b <= 53) {
+    sh = 0;
+    q = (unsigned long long)D[0] | ((unsigned long long)D[1] << 32);
+    up = (2 * r > n) || (2 * r == n && (q & 1));
+  } else {
+    sh = b - 53;
+    const int w = sh >> 5, o = sh & 31;
+    q = ((unsigned long long)D[w] | ((unsigned long long)D[w + 1] << 32)) >> o;
+    if (o) q |= (unsigned long long)D[w + 2] << (64 - o);
+    q &= (1ull << 53) - 1;
+    const int rpos = sh - 1;
+    const unsigned int rbit = (D[rpos >> 5] >> (rpos & 31)) & 1u;
+    unsigned int sticky = D[rpos >> 5] & ((1u << (rpos & 31)) - 1u);
+    for (int i = 0; i < (rpos >> 5); i++) sticky |= D[i];
+    up = rbit && (sticky || r != 0 || (q & 1));
+  }
+  if (up) q += 1;
+  if (q == 0) return 0;                               // rounds to zero -> +0
+  if (q < (1ull << 52)) return sign | q;              // denormal
+  if (q == (1ull << 53)) {
+    q = 1ull << 52;
+    sh += 1;
+  }
+  const unsigned long long E = (unsigned long long)sh + 1;
   if (E >= 2047) return sign | 0x7FF0000000000000ull;
   return sign | (E << 52) | (q - (1ull << 52));
 }
@@ -257,18 +359,18 @@ __device__ __forceinline__ void carry_step_regs(long long &A, long long &B, int 
 }
 
 // Round sum c[i] 2^(32i-1075) (67 int64 chunks in LDS, |c[i]| < 2^62) to
-// binary64 bits, ties to even; specials take precedence.  Called by one
-// whole wavefront (all 64 lanes active); returns the same bits in every
-// lane.  Two parallel carry steps leave every digit below the top in
-// [-1, 2^32]; in the rare case that a digit sits exactly on a bound the
-// serial routine finishes the job (lane 0, D = 70 words of scratch).
+// format F, ties to even; specials take precedence.  Called by one whole
+// wavefront (all 64 lanes active); returns the same bits in every lane.  Two
+// parallel carry steps leave every digit below the top in [-1, 2^32]; in
+// the rare case that a digit sits exactly on a bound the serial routine
+// finishes the job (lane 0, D = 70 words of scratch).
+template <class F>
 __device__ inline unsigned long long round_chunks_wave(const long long *c, unsigned long long pos_inf,
                                                        unsigned long long neg_inf, unsigned long long nan_bits,
                                                        unsigned int *D, int lane) {
-  if (nan_bits) return nan_bits | (1ull << 51);
-  if (pos_inf && neg_inf) return 0x7FF8000000000000ull;
-  if (pos_inf) return 0x7FF0000000000000ull;
-  if (neg_inf) return 0xFFF0000000000000ull;
+  bool has;
+  const unsigned long long sp = special_result<F>(pos_inf, neg_inf, nan_bits, &has);
+  if (has) return sp;
   long long A = c[lane];
   long long B = (lane < 3) ? c[64 + lane] : 0;
   carry_step_regs(A, B, lane);
@@ -279,7 +381,7 @@ __device__ inline unsigned long long round_chunks_wave(const long long *c, unsig
   const bool edgeB = (lane < 2) && ((B < 0) || (B > 0xFFFFFFFFll));
   if (__ballot(edgeA || edgeB) != 0ull) {
     unsigned long long r = 0;
-    if (lane == 0) r = round_chunks(c, 0ull, 0ull, 0ull, D);
+    if (lane == 0) r = round_chunks<F>(c, 0ull, 0ull, 0ull, D);
     return readlane_u64(r, 0);
   }
   const long long top = (long long)readlane_u64((unsigned long long)B, 2);
@@ -291,7 +393,7 @@ __device__ inline unsigned long long round_chunks_wave(const long long *c, unsig
     // two's-complement negation: digits below the lowest nonzero one stay 0,
     // that digit becomes 2^32 - d, the digits above are complemented, and the
     // top becomes -top - 1 (or -top if every lower digit is zero)
-    sign = 1ull << 63;
+    sign = 1ull << F::SIGN;
     const unsigned long long nzA = __ballot(dA != 0u);
     const unsigned long long nzB = __ballot(lane < 2 && dB != 0u);
     int k;
@@ -320,15 +422,12 @@ __device__ inline unsigned long long round_chunks_wave(const long long *c, unsig
   };
   const unsigned int Dt = digit(t);
   const int Bl = 32 * t + 32 - __clz(Dt);          // bit length of X (units 2^-1075)
-  if (Bl <= 53) {
-    const unsigned long long X = (unsigned long long)digit(0) | ((unsigned long long)digit(1) << 32);
-    return sign | (X >> 1);
-  }
-  const int sh = Bl - 53;
+  int sh = Bl - F::P;
+  if (sh < F::U) sh = F::U;
   const int w = sh >> 5, o = sh & 31;
   unsigned long long q = ((unsigned long long)digit(w) | ((unsigned long long)digit(w + 1) << 32)) >> o;
   if (o) q |= (unsigned long long)digit(w + 2) << (64 - o);
-  q &= (1ull << 53) - 1;
+  q &= (1ull << F::P) - 1;
   const int rpos = sh - 1;
   const int rw = rpos >> 5;
   const unsigned int rd = digit(rw);
@@ -338,11 +437,10 @@ __device__ inline unsigned long long round_chunks_wave(const long long *c, unsig
   const unsigned long long belowA = (rw >= 64) ? mA : (rw > 0 ? (mA & ((1ull << rw) - 1ull)) : 0ull);
   const unsigned long long belowB = (rw > 64) ? (mB & ((1ull << (rw - 64)) - 1ull)) : 0ull;
   sticky = sticky || belowA || belowB;
-  unsigned long long E = (unsigned long long)sh;
   if (rbit && (sticky || (q & 1))) q += 1;
-  if (q == (1ull << 53)) { q = 1ull << 52; E += 1; }
-  if (E >= 2047) return sign | 0x7FF0000000000000ull;
-  return sign | (E << 52) | (q - (1ull << 52));
+  unsigned long long bits = ((unsigned long long)(sh - F::U) << (F::P - 1)) + q;
+  if ((bits >> (F::P - 1)) >= F::EMAX) bits = F::EMAX << (F::P - 1);
+  return sign | bits;
 }
 
 }  // namespace exsum

@@ -36,6 +36,24 @@ hipError_t launch_small(const double *x, int64_t n, MergeRows *M, double *out, h
 hipError_t launch_inexact(const double *x, int64_t n, double *partials, unsigned int *ticket,
                           double *out, hipStream_t s, int grid);
 
+// Further sums over the same path (kernels_sum.hip): the small-only kernel
+// when `small`, else the large kernel in its default variant (op_block()
+// threads, 4 positions per thread per tile).
+hipError_t launch_sqnorm(const double *x, int64_t n, double *out, MergeRows *M, hipStream_t s, int grid,
+                         bool small, int precombine);
+hipError_t launch_dot(const double *x, const double *y, int64_t n, double *out, MergeRows *M, hipStream_t s,
+                      int grid, bool small, int precombine);
+hipError_t launch_mean(const double *x, int64_t n, double *out, MergeRows *M, hipStream_t s, int grid, bool small,
+                       int precombine);
+hipError_t launch_f32(const float *x, int64_t n, float *out, MergeRows *M, hipStream_t s, int grid, bool small,
+                      int precombine);
+hipError_t launch_acc_add(const double *x, int64_t n, GlobalAcc *acc, MergeRows *M, hipStream_t s, int grid,
+                          bool small, int precombine);
+hipError_t launch_acc_zero(GlobalAcc *acc, hipStream_t s);
+hipError_t launch_acc_merge(GlobalAcc *dst, const GlobalAcc *src, hipStream_t s);
+hipError_t launch_acc_round(const GlobalAcc *acc, double *out, hipStream_t s);
+int op_block();
+
 // Segmented sums (kernels_seg.hip).
 size_t global_acc_bytes();
 // Two launches: short segments (at most small_max terms) by `short_grid`

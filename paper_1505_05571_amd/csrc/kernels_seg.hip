@@ -102,7 +102,7 @@ __global__ __launch_bounds__(BLOCK) void seg_long_kernel(const double *__restric
       if (s1 - s0 <= small_max) continue;              // short: the other kernel's
       const long long a = s0 > lo_w ? s0 : lo_w;
       const long long b = s1 < hi_w ? s1 : hi_w;
-      accumulate_range<BLOCK, VEC, DEPTH, kCarryMode>(S.L, x, a, b, precombine, tile);
+      accumulate_range<BLOCK, VEC, DEPTH, kCarryMode>(S.L, SrcF64{x}, a, b, precombine, tile);
       final_flush<BLOCK, true, kCarryMode>(S.L);
       const bool split = (s0 < lo_w) || (s1 > hi_w);
       unsigned int expected = 1;
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(BLOCK) void seg_short_kernel(const double *__restri
       const long long s1 = (long long)readlane_u64(ov, k + 1);
       if (s1 - s0 > small_max) continue;               // long: the other kernel's
       small_wave_zero<kShortCopies>(acc, spec, lane);
-      small_wave_accumulate<kShortCopies>(acc, spec, x, s0, s1, lane);
+      small_wave_accumulate<kShortCopies>(acc, spec, SrcF64{x}, s0, s1, lane);
       wave_merge_and_round(acc, spec, D, nullptr, 1u, &out[i0 + k], lane);
     }
   }

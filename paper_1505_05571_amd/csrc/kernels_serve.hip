@@ -46,7 +46,7 @@ __global__ __launch_bounds__(BLOCK) void piece_kernel(const Piece *__restrict__ 
     for (int p = (int)blockIdx.x * NW + wave; p < nshort; p += (int)gridDim.x * NW) {
       const Piece pc = P[p];
       small_wave_zero<kPieceCopies>(acc, spec, lane);
-      small_wave_accumulate<kPieceCopies>(acc, spec, pc.x, 0, pc.n, lane);
+      small_wave_accumulate<kPieceCopies>(acc, spec, SrcF64{pc.x}, 0, pc.n, lane);
       GlobalAcc *g = pc.expected == 1u ? nullptr : &slots[pc.slot];
       wave_merge_and_round(acc, spec, D, g, pc.expected, pc.out, lane);
     }
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(BLOCK) void piece_kernel(const Piece *__restrict__ 
   unsigned int tile = 0;
   for (int p = nshort + (int)blockIdx.x; p < np; p += (int)gridDim.x) {
     const Piece pc = P[p];
-    accumulate_range<BLOCK, VEC, DEPTH, kCarryMode>(S.L, pc.x, 0, pc.n, precombine, tile);
+    accumulate_range<BLOCK, VEC, DEPTH, kCarryMode>(S.L, SrcF64{pc.x}, 0, pc.n, precombine, tile);
     final_flush<BLOCK, true, kCarryMode>(S.L);
     GlobalAcc *g = pc.expected == 1u ? nullptr : &slots[pc.slot];
     merge_and_round(S.L.small, S.L.spec, &S.L.ticket, S.L.D, g, pc.expected, pc.out);

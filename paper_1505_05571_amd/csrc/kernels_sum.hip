@@ -15,9 +15,8 @@
 namespace exsum {
 namespace {
 
-template <int BLOCK, int VEC, int DEPTH, int MODE>
-__global__ __launch_bounds__(BLOCK) void large_kernel(const double *__restrict__ x, long long n,
-                                                      MergeRows *__restrict__ M, double *__restrict__ out,
+template <int BLOCK, int VEC, int DEPTH, int MODE, class Src, class Fin>
+__global__ __launch_bounds__(BLOCK) void large_kernel(Src src, long long n, MergeRows *__restrict__ M, Fin fin,
                                                       int precombine) {
   __shared__ LargeShared S;
   const int tid = threadIdx.x;
@@ -27,17 +26,16 @@ __global__ __launch_bounds__(BLOCK) void large_kernel(const double *__restrict__
   const long long r0 = n * (long long)blockIdx.x / G;
   const long long r1 = n * (long long)(blockIdx.x + 1) / G;
   unsigned int tile = 0;
-  accumulate_range<BLOCK, VEC, DEPTH, MODE>(S, x, r0, r1, precombine, tile);
+  accumulate_range<BLOCK, VEC, DEPTH, MODE>(S, src, r0, r1, precombine, tile);
   final_flush<BLOCK, false, MODE>(S);
-  merge_rows_and_round(S.small, S.spec, S.bcast, S.D, M, out);
+  merge_rows_and_finish(S.small, S.spec, S.bcast, S.D, M, fin);
 }
 
 // Small-only kernel: every wavefront sums a contiguous part into its own
 // small superaccumulator; the workgroup adds its wavefronts' accumulators
 // (each below 2^33 per chunk after the final carry step) and merges.
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void small_kernel(const double *__restrict__ x, long long n,
-                                                      MergeRows *__restrict__ M, double *__restrict__ out) {
+template <int BLOCK, class Src, class Fin>
+__global__ __launch_bounds__(BLOCK) void small_kernel(Src src, long long n, MergeRows *__restrict__ M, Fin fin) {
   constexpr int NW = BLOCK / 64;
   __shared__ long long s_acc[NW][small_acc_words<1>()];
   __shared__ long long s_tot[68];
@@ -52,7 +50,7 @@ __global__ __launch_bounds__(BLOCK) void small_kernel(const double *__restrict__
   const long long r0 = n * (long long)blockIdx.x / G, r1 = n * (long long)(blockIdx.x + 1) / G;
   const long long len = r1 - r0;
   const long long w0 = r0 + len * wave / NW, w1 = r0 + len * (wave + 1) / NW;
-  small_wave_accumulate<1>(s_acc[wave], s_spec, x, w0, w1, lane);
+  small_wave_accumulate<1>(s_acc[wave], s_spec, src, w0, w1, lane);
   __syncthreads();
   if (tid < 68) {
     long long t = 0;
@@ -60,7 +58,41 @@ __global__ __launch_bounds__(BLOCK) void small_kernel(const double *__restrict__
     for (int w = 0; w < NW; w++) t += s_acc[w][tid];
     s_tot[tid] = t;
   }
-  merge_rows_and_round(s_tot, s_spec, s_flag, s_D, M, out);
+  merge_rows_and_finish(s_tot, s_spec, s_flag, s_D, M, fin);
+}
+
+// The streaming accumulator's own kernels (one wavefront each).
+__global__ __launch_bounds__(64) void acc_zero_kernel(GlobalAcc *acc) {
+  unsigned long long *w = reinterpret_cast<unsigned long long *>(acc);
+  for (int i = threadIdx.x; i < (int)(sizeof(GlobalAcc) / 8); i += 64) w[i] = 0ull;
+}
+
+__global__ __launch_bounds__(64) void acc_merge_kernel(GlobalAcc *dst, const GlobalAcc *src) {
+  __shared__ long long c[68];
+  const int lane = threadIdx.x;
+  c[lane] = (long long)(dst->chunk[lane] + src->chunk[lane]);
+  if (lane < 4) c[64 + lane] = (long long)(dst->chunk[64 + lane] + src->chunk[64 + lane]);
+  __builtin_amdgcn_wave_barrier();
+  carry_step(c, lane);
+  dst->chunk[lane] = (unsigned long long)c[lane];
+  if (lane < 4) dst->chunk[64 + lane] = (unsigned long long)c[64 + lane];
+  if (lane == 0) {
+    dst->pos_inf |= src->pos_inf;
+    dst->neg_inf |= src->neg_inf;
+    if (src->nan_bits > dst->nan_bits) dst->nan_bits = src->nan_bits;
+  }
+}
+
+__global__ __launch_bounds__(64) void acc_round_kernel(const GlobalAcc *acc, double *out) {
+  __shared__ long long c[68];
+  __shared__ unsigned int D[70];
+  const int lane = threadIdx.x;
+  c[lane] = (long long)acc->chunk[lane];
+  if (lane < 4) c[64 + lane] = (long long)acc->chunk[64 + lane];
+  __builtin_amdgcn_wave_barrier();
+  const unsigned long long r =
+      round_chunks_wave<FmtF64>(c, acc->pos_inf, acc->neg_inf, acc->nan_bits, D, lane);
+  if (lane == 0) out[0] = __longlong_as_double((long long)r);
 }
 
 // Inexact comparator: ordinary binary64 additions per thread (2*VEC
@@ -134,6 +166,8 @@ __global__ __launch_bounds__(BLOCK) void inexact_kernel(const double *__restrict
 
 }  // namespace
 
+constexpr int kOpBlock = 1024;
+
 // Built variants (block, vec, depth, mode).  Count mode needs
 // 2*block*vec < 4096 (the count bound per tile); carry mode does not.
 #define EXSUM_LARGE_VARIANTS(X) \
@@ -151,11 +185,11 @@ __global__ __launch_bounds__(BLOCK) void inexact_kernel(const double *__restrict
 hipError_t launch_large(const double *x, int64_t n, MergeRows *M, double *out, hipStream_t s, int block,
                         int vec, int depth, int mode, int grid, int precombine) {
   if (grid < 1) grid = 1;
-#define EXSUM_LAUNCH(B, V, D, MD)                                                                       \
-  if (block == B && vec == V && depth == D && mode == MD) {                                             \
-    hipLaunchKernelGGL((large_kernel<B, V, D, MD>), dim3(grid), dim3(B), 0, s, x, (long long)n, M, out, \
-                       precombine);                                                                     \
-    return hipGetLastError();                                                                           \
+#define EXSUM_LAUNCH(B, V, D, MD)                                                                             \
+  if (block == B && vec == V && depth == D && mode == MD) {                                                   \
+    hipLaunchKernelGGL((large_kernel<B, V, D, MD, SrcF64, FinF64>), dim3(grid), dim3(B), 0, s, SrcF64{x},     \
+                       (long long)n, M, FinF64{out}, precombine);                                             \
+    return hipGetLastError();                                                                                 \
   }
   EXSUM_LARGE_VARIANTS(EXSUM_LAUNCH)
 #undef EXSUM_LAUNCH
@@ -172,9 +206,71 @@ bool large_variant_exists(int block, int vec, int depth, int mode) {
 
 hipError_t launch_small(const double *x, int64_t n, MergeRows *M, double *out, hipStream_t s, int grid) {
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL((small_kernel<256>), dim3(grid), dim3(256), 0, s, x, (long long)n, M, out);
+  hipLaunchKernelGGL((small_kernel<256, SrcF64, FinF64>), dim3(grid), dim3(256), 0, s, SrcF64{x}, (long long)n, M,
+                     FinF64{out});
   return hipGetLastError();
 }
+
+// Other sources and finishers: the small kernel, or the large kernel in its
+// default variant (1024 threads, 4 positions per thread per tile, 2 tiles in
+// flight, carry-triggered transfers).
+namespace {
+template <class Src, class Fin>
+hipError_t launch_op(const Src &src, int64_t n, const Fin &fin, MergeRows *M, hipStream_t s, int grid, bool small,
+                     int precombine) {
+  if (grid < 1) grid = 1;
+  if (small)
+    hipLaunchKernelGGL((small_kernel<256, Src, Fin>), dim3(grid), dim3(256), 0, s, src, (long long)n, M, fin);
+  else
+    hipLaunchKernelGGL((large_kernel<kOpBlock, 4, 2, kCarryMode, Src, Fin>), dim3(grid), dim3(kOpBlock), 0, s, src,
+                       (long long)n, M, fin, precombine);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_sqnorm(const double *x, int64_t n, double *out, MergeRows *M, hipStream_t s, int grid, bool small,
+                         int precombine) {
+  return launch_op(SrcSq{{x}}, n, FinF64{out}, M, s, grid, small, precombine);
+}
+
+hipError_t launch_dot(const double *x, const double *y, int64_t n, double *out, MergeRows *M, hipStream_t s,
+                      int grid, bool small, int precombine) {
+  if (((reinterpret_cast<uintptr_t>(x) ^ reinterpret_cast<uintptr_t>(y)) & 15) == 0)
+    return launch_op(SrcDot<true>{x, y}, n, FinF64{out}, M, s, grid, small, precombine);
+  return launch_op(SrcDot<false>{x, y}, n, FinF64{out}, M, s, grid, small, precombine);
+}
+
+hipError_t launch_mean(const double *x, int64_t n, double *out, MergeRows *M, hipStream_t s, int grid, bool small,
+                       int precombine) {
+  return launch_op(SrcF64{x}, n, FinMean{out, (unsigned long long)n}, M, s, grid, small, precombine);
+}
+
+hipError_t launch_f32(const float *x, int64_t n, float *out, MergeRows *M, hipStream_t s, int grid, bool small,
+                      int precombine) {
+  return launch_op(SrcF32{x}, n, FinF32{out}, M, s, grid, small, precombine);
+}
+
+hipError_t launch_acc_add(const double *x, int64_t n, GlobalAcc *acc, MergeRows *M, hipStream_t s, int grid,
+                          bool small, int precombine) {
+  return launch_op(SrcF64{x}, n, FinAcc{acc}, M, s, grid, small, precombine);
+}
+
+hipError_t launch_acc_zero(GlobalAcc *acc, hipStream_t s) {
+  hipLaunchKernelGGL(acc_zero_kernel, dim3(1), dim3(64), 0, s, acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_acc_merge(GlobalAcc *dst, const GlobalAcc *src, hipStream_t s) {
+  hipLaunchKernelGGL(acc_merge_kernel, dim3(1), dim3(64), 0, s, dst, src);
+  return hipGetLastError();
+}
+
+hipError_t launch_acc_round(const GlobalAcc *acc, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(acc_round_kernel, dim3(1), dim3(64), 0, s, acc, out);
+  return hipGetLastError();
+}
+
+int op_block() { return kOpBlock; }
 
 hipError_t launch_inexact(const double *x, int64_t n, double *partials, unsigned int *ticket, double *out,
                           hipStream_t s, int grid) {

@@ -191,3 +191,24 @@ def test_server_host_side_checks(lib):
     cnt = ctypes.c_int64(0)
     assert lib.exsum_server_plan(None, P(lens.ctypes.data), 1, 0, None, None, None, None, None, None,
                                  ctypes.byref(cnt)) == 1
+
+
+def test_further_reductions_host_checks(lib):
+    import ctypes
+    P = ctypes.c_void_p
+    assert lib.exsum_sqnorm_f64(None, 4, P(8), None) == 1
+    assert lib.exsum_sqnorm_f64(P(8), -1, P(8), None) == 1
+    assert lib.exsum_dot_f64(P(8), None, 4, P(8), None) == 1
+    assert lib.exsum_dot_f64(P(8), P(8), 4, None, None) == 1
+    assert lib.exsum_mean_f64(P(8), 1 << 40, P(8), None) == 1
+    assert lib.exsum_f32(None, 3, P(8), None) == 1
+    # the accumulator state must be 64-byte aligned device memory
+    assert lib.exsum_acc_zero(None, None) == 1
+    assert lib.exsum_acc_zero(P(64 + 8), None) == 1
+    assert lib.exsum_acc_add_f64(P(64), None, 5, None) == 1
+    assert lib.exsum_acc_add_f64(P(64), P(8), -2, None) == 1
+    assert lib.exsum_acc_add_f64(P(64), None, 0, None) == 0          # nothing to add
+    assert lib.exsum_acc_merge(P(64), P(64), None) == 1              # a state into itself
+    assert lib.exsum_acc_merge(P(64), P(96), None) == 1
+    assert lib.exsum_acc_round_f64(P(64), None, None) == 1
+    assert ex.EXSUM_ACC_BYTES == 576

@@ -1,0 +1,211 @@
+"""GPU parity of the further reductions over the same path: squared norm and
+dot product (products rounded to binary64, then summed exactly), the exact
+mean, binary32 sums, and the streaming accumulator -- bit for bit against
+the oracle, on the small-only and the large path."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1505_05571_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+NAN_A = np.array([0x7FF0000000000001], dtype=np.uint64).view(np.float64)[0]
+
+
+@pytest.fixture(scope="module")
+def ex():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1505_05571_amd as ex
+    ex.load_library()
+    base = ex.exsum_get_config()
+    yield ex
+    ex.exsum_set_config(base)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def u64(t):
+    torch.cuda.synchronize()
+    return int(t.cpu().numpy().view(np.uint64)[0])
+
+
+def u32(t):
+    torch.cuda.synchronize()
+    return int(t.cpu().numpy().view(np.uint32)[0])
+
+
+def paths(ex):
+    """Run the body on the default path choice, small-only and large-only."""
+    base = ex.exsum_get_config()
+    for small_max in (None, 10 ** 12, 0):
+        c = ex.exsum_get_config()
+        for k, _ in c._fields_:
+            setattr(c, k, getattr(base, k))
+        if small_max is not None:
+            c.small_max = small_max
+        ex.exsum_set_config(c)
+        yield small_max
+    ex.exsum_set_config(base)
+
+
+SIZES = [0, 1, 2, 3, 63, 1000, 4096, 4097, 100003, 1000003]
+
+
+def operands(n, seed):
+    x = W.uniform_exponent(n, seed=seed, kmin=-250, kmax=250)
+    y = W.uniform_exponent(n, seed=seed + 1, kmin=-250, kmax=250)
+    return x, y
+
+
+def test_sqnorm_and_dot(ex):
+    for n in SIZES:
+        x, y = operands(n, n)
+        want_sq, want_dot = int(oracle.sqnorm_f64(x)), int(oracle.dot_f64(x, y))
+        xt, yt = dev(x), dev(y)
+        for p in paths(ex):
+            assert u64(ex.exsum_sqnorm_f64(xt)) == want_sq, (n, p)
+            assert u64(ex.exsum_dot_f64(xt, yt)) == want_dot, (n, p)
+
+
+def test_dot_with_operands_of_different_alignment(ex):
+    x, y = operands(300007, 11)
+    xt, yt = dev(x), dev(y)
+    for (a, b, L) in [(0, 1, 300000), (1, 0, 300000), (1, 1, 300001), (3, 6, 250000), (1, 2, 5)]:
+        want = int(oracle.dot_f64(x[a:a + L], y[b:b + L]))
+        for p in paths(ex):
+            assert u64(ex.exsum_dot_f64(xt[a:a + L], yt[b:b + L])) == want, (a, b, L, p)
+
+
+def test_products_that_underflow_overflow_or_are_special(ex):
+    rng = np.random.default_rng(12)
+    n = 20000
+    x = np.ldexp(rng.standard_normal(n), rng.integers(-560, 560, size=n))
+    y = np.ldexp(rng.standard_normal(n), rng.integers(-560, 560, size=n))
+    with np.errstate(over="ignore"):
+        keep = np.isfinite(x * y)                                   # drop products that overflow
+    x, y = x[keep], y[keep]
+    want = int(oracle.dot_f64(x, y))
+    for p in paths(ex):
+        assert u64(ex.exsum_dot_f64(dev(x), dev(y))) == want, p
+    base = W.uniform_exponent(5000, seed=13, kmin=-10, kmax=10)
+    for xs, ys in (([math.inf], [0.0]), ([math.inf], [2.0]), ([NAN_A], [3.0]), ([1e200], [1e200]),
+                   ([1e200, -1e200], [1e200, 1e200]), ([-math.inf, 4.0], [1.0, math.inf])):
+        x = base.copy()
+        y = base.copy()
+        x[[10, 4000][:len(xs)]] = xs
+        y[[10, 4000][:len(ys)]] = ys
+        want = int(oracle.dot_f64(x, y))
+        for p in paths(ex):
+            assert u64(ex.exsum_dot_f64(dev(x), dev(y))) == want, (xs, ys, p)
+
+
+def test_mean(ex):
+    for n in SIZES:
+        x = W.uniform_exponent(n, seed=n + 5)
+        want = int(oracle.mean_f64(x))
+        xt = dev(x)
+        for p in paths(ex):
+            assert u64(ex.exsum_mean_f64(xt)) == want, (n, p)
+    dmax = np.finfo(np.float64).max
+    cases = [
+        [1e15, -1e15, 0.1],                      # the worked example: the mean is fl(0.1/3)
+        [dmax, dmax, dmax],                      # the sum overflows, the mean does not
+        [5e-324, 0.0, 0.0],                      # 2^-1074 / 3 rounds to zero: +0
+        [5e-324, 5e-324, 0.0],                   # 2^-1075 * 4/3 rounds to 2^-1074
+        [-3.0, 1.0],
+        [1.0] * 7 + [2.0 ** -60],
+    ]
+    for vals in cases:
+        x = np.array(vals, dtype=np.float64)
+        want = int(oracle.mean_f64(x))
+        for p in paths(ex):
+            assert u64(ex.exsum_mean_f64(dev(x))) == want, (vals, p)
+    assert int(oracle.mean_f64(np.array(cases[0]))) == int(np.array([0.1 / 3]).view(np.uint64)[0])
+
+
+def f32_bits(n, seed):
+    rng = np.random.default_rng(seed)
+    b = rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+    e = (b >> np.uint32(23)) & np.uint32(255)
+    b = np.where(e == 255, b ^ np.uint32(1 << 23), b)         # finite only
+    return b.view(np.float32)
+
+
+def test_f32(ex):
+    for n in SIZES:
+        for x in (f32_bits(n, n), (W.small_normal(n, seed=n)).astype(np.float32)):
+            want = int(oracle.sum_f32(x))
+            xt = dev(x)
+            for p in paths(ex):
+                assert u32(ex.exsum_f32(xt)) == want, (n, p)
+    fmax = np.finfo(np.float32).max
+    tiny = np.float32(1e-45)
+    nan_a = np.array([0x7F800001], dtype=np.uint32).view(np.float32)[0]
+    nan_b = np.array([0xFFC01234], dtype=np.uint32).view(np.float32)[0]
+    cases = [
+        [fmax, fmax, -fmax],                     # overflowing partial sums, finite result
+        [fmax, fmax],                            # overflow to +Inf
+        [tiny] * 5,                              # denormal sums
+        [np.float32(1.0), tiny],                 # rounds back to 1
+        [np.float32(np.inf), np.float32(-np.inf)],
+        [nan_a, nan_b, np.float32(2.0)],
+        [np.float32(-0.0), np.float32(-0.0)],    # exact zero: +0
+    ]
+    for vals in cases:
+        x = np.array(vals, dtype=np.float32)
+        big = np.zeros(50001, dtype=np.float32)
+        big[::50001 // x.size][:x.size] = x
+        want = int(oracle.sum_f32(x))
+        assert int(oracle.sum_f32(big)) == want
+        for p in paths(ex):
+            assert u32(ex.exsum_f32(dev(x))) == want, (vals, p)
+            assert u32(ex.exsum_f32(dev(big))) == want, (vals, p)
+    x = f32_bits(300003, 7)
+    xt = dev(x)
+    for lo, hi in [(1, 300003), (2, 299999), (3, 300000), (1, 4)]:
+        assert u32(ex.exsum_f32(xt[lo:hi])) == int(oracle.sum_f32(x[lo:hi])), (lo, hi)
+
+
+def test_accumulator_add_merge_round(ex):
+    parts = [W.uniform_exponent(n, seed=20 + n) for n in (0, 1, 1000, 4097, 300001)]
+    parts.append(W.adversarial(4000, seed=21))
+    whole = np.concatenate(parts)
+    want = int(oracle.sum_f64(whole))
+    for p in paths(ex):
+        a = ex.Accumulator()
+        b = ex.Accumulator()
+        running = []
+        for i, part in enumerate(parts):
+            (a if i % 2 == 0 else b).add(dev(part))
+            running.append(u64(a.round()))
+        assert running[-1] == int(oracle.sum_f64(np.concatenate(parts[0::2]))), p
+        a.merge(b)
+        assert u64(a.round()) == want, p
+        assert u64(a.round()) == want                  # rounding leaves the state as it was
+        a.zero()
+        assert u64(a.round()) == 0
+
+
+def test_accumulator_many_updates_and_specials(ex):
+    dmax = np.finfo(np.float64).max
+    a = ex.Accumulator()
+    chunk = np.array([dmax, -dmax / 2, 2.0 ** -1074], dtype=np.float64)
+    ct = dev(chunk)
+    for _ in range(300):
+        a.add(ct)
+    want = int(oracle.sum_f64(np.tile(chunk, 300)))
+    assert u64(a.round()) == want                      # +Inf: the exact sum overflows
+    b = ex.Accumulator().add(dev(np.array([-dmax / 2] * 300, dtype=np.float64)))
+    a.merge(b)
+    want = int(oracle.sum_f64(np.concatenate([np.tile(chunk, 300), [-dmax / 2] * 300])))
+    assert u64(a.round()) == want                      # back to 300 * 2^-1074
+    c = ex.Accumulator().add(dev(np.array([1.0, NAN_A])))
+    a.merge(c)
+    assert u64(a.round()) == int(oracle.sum_f64(np.array([NAN_A])))
