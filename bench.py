@@ -51,6 +51,10 @@ WORKLOADS = {
     "small_normal": "small_normal n=1000 (sign uniform, |N(0,1)| 2^k, k in [-20,20]); latency",
     "segments": "segments nseg=65536 lognormal(median 1000, sigma 2) clipped [1,1e6]; one batched call",
     "copy": "device-to-device copy of 800 MB (reference for HBM bandwidth and counter calibration)",
+    "dot": "dot product of two 5e7-term vectors (uniform_exponent draws, exponents [-250, 250]; 800 MB read)",
+    "sqnorm": "squared norm of 1e8 terms (uniform_exponent draws, exponents [-250, 250]; 800 MB)",
+    "mean": "exact mean of the 1e8-term uniform_exponent input (800 MB)",
+    "f32": "binary32 sum of 2e8 terms (sign, mantissa and exponent in [-60, 60] uniform; 800 MB)",
     "serve": "served requests: lengths log-uniform [10, 1e8], slices of a resident 1e8-term uniform_exponent pool, "
              "Poisson arrivals at rho = 0.8 and 2 of the serial service rate",
 }
@@ -215,6 +219,101 @@ def serve_bench(args):
     print(json.dumps(result), flush=True)
 
 
+OPS = ("dot", "sqnorm", "mean", "f32")
+
+
+def op_bench(args):
+    """The further reductions (dot product, squared norm, mean, binary32
+    sum) over the same path: throughput, roofline of the kernel, parity with
+    the oracle and the oracle's own rate on a bounded prefix."""
+    import torch
+    import oracle
+    import paper_1505_05571_amd as ex
+    from paper_1505_05571_amd import workloads as W
+    ex.load_library()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    w = args.workload
+    if w == "dot":
+        n = 5 * 10 ** 7
+        xs = (W.uniform_exponent(n, seed=0, kmin=-250, kmax=250), W.uniform_exponent(n, seed=1, kmin=-250, kmax=250))
+        bytes_per_term = 16
+    elif w == "f32":
+        n = 2 * 10 ** 8
+        rng = np.random.default_rng(0)
+        b = ((rng.integers(0, 2, size=n, dtype=np.uint32) << np.uint32(31))
+             | (rng.integers(127 - 60, 127 + 61, size=n, dtype=np.uint32) << np.uint32(23))
+             | rng.integers(0, 1 << 23, size=n, dtype=np.uint32))
+        xs = (b.view(np.float32),)
+        bytes_per_term = 4
+    else:
+        n = 10 ** 8
+        xs = (W.uniform_exponent(n, seed=0, kmin=-250, kmax=250) if w == "sqnorm" else W.uniform_exponent(n, seed=0),)
+        bytes_per_term = 8
+    bufs = [[torch.from_numpy(a).to(dev) for a in xs] for _ in range(2)]
+    out = torch.empty(1, dtype=torch.float32 if w == "f32" else torch.float64, device=dev)
+    fn = {"dot": lambda t: ex.exsum_dot_f64(t[0], t[1], out=out, stream=stream),
+          "sqnorm": lambda t: ex.exsum_sqnorm_f64(t[0], out=out, stream=stream),
+          "mean": lambda t: ex.exsum_mean_f64(t[0], out=out, stream=stream),
+          "f32": lambda t: ex.exsum_f32(t[0], out=out, stream=stream)}[w]
+    inexact = {"dot": lambda t: torch.dot(t[0], t[1]), "sqnorm": lambda t: torch.dot(t[0], t[0]),
+               "mean": lambda t: torch.mean(t[0]), "f32": lambda t: torch.sum(t[0])}[w]
+    for i in range(args.warmup):
+        fn(bufs[i & 1])
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for i in range(args.steps):
+        fn(bufs[i & 1])
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    avg = ev0.elapsed_time(ev1) / 1e3 / args.steps
+    got = out.cpu().numpy().view(np.uint32 if w == "f32" else np.uint64)[0]
+    orc = {"dot": lambda a: oracle.dot_f64(a[0], a[1]), "sqnorm": lambda a: oracle.sqnorm_f64(a[0]),
+           "mean": lambda a: oracle.mean_f64(a[0]), "f32": lambda a: oracle.sum_f32(a[0])}[w]
+    parity = bool(int(got) == int(orc(xs)))
+    for i in range(3):
+        inexact(bufs[i & 1])
+    torch.cuda.synchronize()
+    s_ = torch.cuda.Event(enable_timing=True)
+    e_ = torch.cuda.Event(enable_timing=True)
+    s_.record(stream)
+    for i in range(20):
+        inexact(bufs[i & 1])
+    e_.record(stream)
+    torch.cuda.synchronize()
+    t_inexact = s_.elapsed_time(e_) / 1e3 / 20
+    bytes_per_step = float(bytes_per_term) * n
+    result = {
+        "metric": "exact-sum GB/s (0-ulp vs oracle) and % of HBM peak vs inexact GPU sum",
+        "value": round(bytes_per_step * args.steps / wall / 1e9, 1), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int64", "data": "synthetic",
+        "config": {"workload": WORKLOADS[w], "n_terms": n, "input_dtype": "f32" if w == "f32" else "f64",
+                   "seed": 0, "terms_per_s": round(n * args.steps / wall, 1)},
+        "roofline": {"bound": "hbm", "achieved": round(bytes_per_step / avg / 1e9, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(bytes_per_step / avg / 1e9 / HBM_PEAK_GBS, 4), "traffic": None},
+        "inexact": {"torch_GBs": round(bytes_per_step / t_inexact / 1e9, 1),
+                    "exact_over_inexact_time": round(avg / t_inexact, 3)},
+        "parity": parity,
+    }
+    if not args.no_cpu_baseline:
+        # the oracle, single-threaded, on a prefix sized to about 10 s
+        m = max(n // 64, 1)
+        part = tuple(a[:m] for a in xs)
+        t0 = time.perf_counter()
+        orc(part)
+        el = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": round(bytes_per_term * m / el / 1e9, 4), "unit": "GB/s", "cores": 1,
+                                  "kind": "oracle", "sample": "first %d of %d terms, one thread" % (m, n)}
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,6 +332,8 @@ def main():
 
     if args.workload == "serve":
         return serve_bench(args)
+    if args.workload in OPS:
+        return op_bench(args)
     import torch
     import paper_1505_05571_amd as ex
     ex.load_library()

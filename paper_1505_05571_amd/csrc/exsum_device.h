@@ -288,18 +288,30 @@ __device__ inline unsigned long long round_mean_f64(const long long *c, unsigned
   const unsigned long long sp = special_result<FmtF64>(pos_inf, neg_inf, nan_bits, &has);
   if (has) return sp;
   const unsigned long long sign = (unsigned long long)magnitude_digits(c, D) << 63;
-  // A = X / 2, then Q = A / n in place, 16 bits at a time (r < n < 2^48)
+  // A = X / 2, then Q = A / n in place, 16 bits at a time: each partial
+  // dividend is below n * 2^16 <= 2^56, its quotient (below 2^16) is first
+  // estimated with a binary64 multiply by 1/n and then made exact with
+  // integer corrections of the remainder (the estimate is off by a few
+  // units at most)
   for (int i = 0; i < 67; i++) D[i] = (D[i] >> 1) | (D[i + 1] << 31);
+  const long long nn = (long long)n;
+  const double inv = 1.0 / (double)n;
   unsigned long long r = 0;
   for (int i = 66; i >= 0; i--) {
     const unsigned int d = D[i];
-    r = (r << 16) | (d >> 16);
-    const unsigned long long qh = r / n;
-    r -= qh * n;
-    r = (r << 16) | (d & 0xFFFFu);
-    const unsigned long long ql = r / n;
-    r -= ql * n;
-    D[i] = (unsigned int)((qh << 16) | ql);
+    long long cur = (long long)((r << 16) | (d >> 16));
+    long long qe = (long long)((double)cur * inv);
+    long long rem = cur - qe * nn;
+    while (rem < 0) { qe -= 1; rem += nn; }
+    while (rem >= nn) { qe += 1; rem -= nn; }
+    const unsigned long long qh = (unsigned long long)qe;
+    cur = (rem << 16) | (long long)(d & 0xFFFFu);
+    qe = (long long)((double)cur * inv);
+    rem = cur - qe * nn;
+    while (rem < 0) { qe -= 1; rem += nn; }
+    while (rem >= nn) { qe += 1; rem -= nn; }
+    r = (unsigned long long)rem;
+    D[i] = (unsigned int)((qh << 16) | (unsigned long long)qe);
   }
   int t = 66;
   while (t >= 0 && D[t] == 0) t--;
