@@ -60,7 +60,6 @@ struct LargeShared {
   unsigned int flag[4];                 // "some chunk marked", by tile mod 3
   unsigned int ticket;
   unsigned int bcast[4];                // broadcast slots
-  unsigned int D[70];                   // rounding scratch
 };
 
 __device__ __forceinline__ void large_init(LargeShared &S, int tid, int block) {
@@ -604,14 +603,13 @@ __device__ __forceinline__ unsigned int ticket_add(unsigned int *p) {
 // that wrote the result.  Used where few parts meet (a segment cut by
 // workgroup boundaries), so the atomics see little contention.
 __device__ __forceinline__ bool merge_and_round(long long *s_small, unsigned long long *spec,
-                                                unsigned int *s_ticket, unsigned int *s_D,
-                                                GlobalAcc *__restrict__ g, unsigned int expected,
-                                                double *__restrict__ out) {
+                                                unsigned int *s_ticket, GlobalAcc *__restrict__ g,
+                                                unsigned int expected, double *__restrict__ out) {
   const int tid = threadIdx.x;
   __syncthreads();
   if (expected <= 1) {
     if (tid < 64) {
-      const unsigned long long r = round_chunks_wave<FmtF64>(s_small, spec[0], spec[1], spec[2], s_D, tid);
+      const unsigned long long r = round_chunks_wave<FmtF64>(s_small, spec[0], spec[1], spec[2], tid);
       if (tid == 0) out[0] = __longlong_as_double((long long)r);
     }
     __syncthreads();
@@ -640,7 +638,7 @@ __device__ __forceinline__ bool merge_and_round(long long *s_small, unsigned lon
   if (tid == 99) atomicExch(&g->ticket, 0u);
   __syncthreads();
   if (tid < 64) {
-    const unsigned long long r = round_chunks_wave<FmtF64>(s_small, spec[0], spec[1], spec[2], s_D, tid);
+    const unsigned long long r = round_chunks_wave<FmtF64>(s_small, spec[0], spec[1], spec[2], tid);
     if (tid == 0) out[0] = __longlong_as_double((long long)r);
   }
   __syncthreads();
@@ -648,8 +646,8 @@ __device__ __forceinline__ bool merge_and_round(long long *s_small, unsigned lon
 }
 
 // The same for a single wavefront's small accumulator (acc: 68 chunks in
-// LDS, spec: 3 words, D: 70 words of scratch).  All 64 lanes call it.
-__device__ __forceinline__ void wave_merge_and_round(long long *acc, unsigned long long *spec, unsigned int *D,
+// LDS, spec: 3 words).  All 64 lanes call it.
+__device__ __forceinline__ void wave_merge_and_round(long long *acc, unsigned long long *spec,
                                                      GlobalAcc *__restrict__ g, unsigned int expected,
                                                      double *__restrict__ out, int lane) {
   if (expected > 1) {
@@ -679,7 +677,7 @@ __device__ __forceinline__ void wave_merge_and_round(long long *acc, unsigned lo
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   }
-  const unsigned long long r = round_chunks_wave<FmtF64>(acc, spec[0], spec[1], spec[2], D, lane);
+  const unsigned long long r = round_chunks_wave<FmtF64>(acc, spec[0], spec[1], spec[2], lane);
   if (lane == 0) out[0] = __longlong_as_double((long long)r);
 }
 
@@ -720,13 +718,13 @@ __device__ __forceinline__ long long combine_rows(const long long (*rows)[kRowWo
 
 template <class Fin>
 __device__ __forceinline__ bool merge_rows_and_finish(long long *s_small, unsigned long long *spec,
-                                                      unsigned int *s_flag, unsigned int *s_D,
-                                                      MergeRows *__restrict__ M, const Fin &fin) {
+                                                      unsigned int *s_flag, MergeRows *__restrict__ M,
+                                                      const Fin &fin) {
   const int tid = threadIdx.x;
   const unsigned int G = gridDim.x, b = blockIdx.x;
   __syncthreads();
   if (G == 1) {
-    fin(s_small, spec, s_D);
+    fin(s_small, spec);
     __syncthreads();
     return true;
   }
@@ -755,7 +753,7 @@ __device__ __forceinline__ bool merge_rows_and_finish(long long *s_small, unsign
   }
   if (tid == 0) __hip_atomic_store(&M->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
-  fin(s_small, spec, s_D);
+  fin(s_small, spec);
   __syncthreads();
   return true;
 }
@@ -908,16 +906,16 @@ __device__ __forceinline__ void small_wave_accumulate(long long *acc, unsigned l
 // ---------------------------------------------------------------------------
 // Finishers: what the workgroup holding the merged small accumulator does
 // with it.  Called by every thread of that workgroup; c is 68 chunks in LDS
-// (|c[i]| < 2^62), spec the 3 side words, D 70 words of LDS scratch.
+// (|c[i]| < 2^62) and spec the 3 side words.
 // ---------------------------------------------------------------------------
 
 // Round to binary64 (Small: obtaining the correctly rounded result).
 struct FinF64 {
   double *out;
-  __device__ void operator()(long long *c, unsigned long long *spec, unsigned int *D) const {
+  __device__ void operator()(long long *c, unsigned long long *spec) const {
     const int tid = threadIdx.x;
     if (tid < 64) {
-      const unsigned long long r = round_chunks_wave<FmtF64>(c, spec[0], spec[1], spec[2], D, tid);
+      const unsigned long long r = round_chunks_wave<FmtF64>(c, spec[0], spec[1], spec[2], tid);
       if (tid == 0) out[0] = __longlong_as_double((long long)r);
     }
   }
@@ -927,10 +925,10 @@ struct FinF64 {
 // Introduction).
 struct FinF32 {
   float *out;
-  __device__ void operator()(long long *c, unsigned long long *spec, unsigned int *D) const {
+  __device__ void operator()(long long *c, unsigned long long *spec) const {
     const int tid = threadIdx.x;
     if (tid < 64) {
-      const unsigned long long r = round_chunks_wave<FmtF32>(c, spec[0], spec[1], spec[2], D, tid);
+      const unsigned long long r = round_chunks_wave<FmtF32>(c, spec[0], spec[1], spec[2], tid);
       if (tid == 0) out[0] = __uint_as_float((unsigned int)r);
     }
   }
@@ -940,10 +938,11 @@ struct FinF32 {
 struct FinMean {
   double *out;
   unsigned long long n;
-  __device__ void operator()(long long *c, unsigned long long *spec, unsigned int *D) const {
-    if (threadIdx.x == 0) {
-      const unsigned long long r = n ? round_mean_f64(c, spec[0], spec[1], spec[2], D, n) : 0ull;
-      out[0] = __longlong_as_double((long long)r);
+  __device__ void operator()(long long *c, unsigned long long *spec) const {
+    const int tid = threadIdx.x;
+    if (tid < 64) {
+      const unsigned long long r = n ? round_mean_wave(c, spec[0], spec[1], spec[2], n, tid) : 0ull;
+      if (tid == 0) out[0] = __longlong_as_double((long long)r);
     }
   }
 };
@@ -955,7 +954,7 @@ struct FinMean {
 // orders the calls that touch one accumulator, so plain accesses suffice.
 struct FinAcc {
   GlobalAcc *acc;
-  __device__ void operator()(long long *c, unsigned long long *spec, unsigned int *) const {
+  __device__ void operator()(long long *c, unsigned long long *spec) const {
     const int tid = threadIdx.x;
     if (tid < 68) c[tid] += (long long)acc->chunk[tid];
     __syncthreads();

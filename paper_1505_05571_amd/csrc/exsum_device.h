@@ -219,134 +219,6 @@ __device__ __forceinline__ unsigned long long special_result(unsigned long long 
   return 0;
 }
 
-// ---- carry propagation and rounding (one thread) ---------------------------
-
-// Magnitude digits of sum c[i] 2^(32i) (i < 67, int64 chunks whose partial
-// sums stay in range): D[0..66] in [0, 2^32), D[67..69] = 0; returns the
-// sign (1 negative).  Serial, one lane; D is 70 words of scratch in LDS.
-__device__ inline int magnitude_digits(const long long *c, unsigned int *D) {
-  long long carry = 0;
-  for (int i = 0; i < 66; i++) {
-    const long long v = c[i] + carry;
-    D[i] = (unsigned int)v;
-    carry = v >> 32;
-  }
-  long long top = c[66] + carry;                      // |top| < 2^31 for any real input
-  D[66] = (unsigned int)top;
-  D[67] = D[68] = D[69] = 0;
-  if (top >= 0) return 0;
-  unsigned long long cy = 1;                          // magnitude by two's-complement negation
-  for (int i = 0; i < 67; i++) {
-    const unsigned long long t = (unsigned long long)(unsigned int)~D[i] + cy;
-    D[i] = (unsigned int)t;
-    cy = t >> 32;
-  }
-  return 1;
-}
-
-// Round the value sum c[i] 2^(32i-1075) to format F, round to nearest, ties
-// to even (Small: obtaining the correctly rounded result); specials take
-// precedence; an exact zero gives +0.  Serial code, run by a single lane.
-template <class F>
-__device__ inline unsigned long long round_chunks(const long long *c, unsigned long long pos_inf,
-                                                  unsigned long long neg_inf, unsigned long long nan_bits,
-                                                  unsigned int *D) {
-  bool has;
-  const unsigned long long sp = special_result<F>(pos_inf, neg_inf, nan_bits, &has);
-  if (has) return sp;
-  const unsigned long long sign = (unsigned long long)magnitude_digits(c, D) << F::SIGN;
-  int t = 66;
-  while (t >= 0 && D[t] == 0) t--;
-  if (t < 0) return 0;                                // exact zero -> +0.0
-  const int Bl = 32 * t + 32 - __builtin_clz(D[t]);  // bit length of X
-  int sh = Bl - F::P;
-  if (sh < F::U) sh = F::U;
-  const int w = sh >> 5, o = sh & 31;
-  unsigned long long q = ((unsigned long long)D[w] | ((unsigned long long)D[w + 1] << 32)) >> o;
-  if (o) q |= (unsigned long long)D[w + 2] << (64 - o);
-  q &= (1ull << F::P) - 1;
-  const int rpos = sh - 1;                            // round bit position (>= 0)
-  const unsigned int rbit = (D[rpos >> 5] >> (rpos & 31)) & 1u;
-  unsigned int sticky = D[rpos >> 5] & ((1u << (rpos & 31)) - 1u);
-  for (int i = 0; i < (rpos >> 5); i++) sticky |= D[i];
-  if (rbit && (sticky || (q & 1))) q += 1;
-  unsigned long long bits = ((unsigned long long)(sh - F::U) << (F::P - 1)) + q;
-  if ((bits >> (F::P - 1)) >= F::EMAX) bits = F::EMAX << (F::P - 1);
-  return sign | bits;
-}
-
-// The exact mean: the value sum c[i] 2^(32i-1075) divided by n >= 1, rounded
-// once to binary64 (Discussion, on a correctly rounded mean).  With A the
-// magnitude in units of 2^-1074 (X/2; X is even), Q = floor(A/n) and
-// R = A mod n: a quotient below 2^53 rounds on R alone, a longer one on its
-// bit below the 53 kept and the sticky OR of the bits further down and R.
-// A mean that rounds to zero is +0.  Serial, one lane; D is 70 words of LDS.
-__device__ inline unsigned long long round_mean_f64(const long long *c, unsigned long long pos_inf,
-                                                    unsigned long long neg_inf, unsigned long long nan_bits,
-                                                    unsigned int *D, unsigned long long n) {
-  bool has;
-  const unsigned long long sp = special_result<FmtF64>(pos_inf, neg_inf, nan_bits, &has);
-  if (has) return sp;
-  const unsigned long long sign = (unsigned long long)magnitude_digits(c, D) << 63;
-  // A = X / 2, then Q = A / n in place, 16 bits at a time: each partial
-  // dividend is below n * 2^16 <= 2^56, its quotient (below 2^16) is first
-  // estimated with a binary64 multiply by 1/n and then made exact with
-  // integer corrections of the remainder (the estimate is off by a few
-  // units at most)
-  for (int i = 0; i < 67; i++) D[i] = (D[i] >> 1) | (D[i + 1] << 31);
-  const long long nn = (long long)n;
-  const double inv = 1.0 / (double)n;
-  unsigned long long r = 0;
-  for (int i = 66; i >= 0; i--) {
-    const unsigned int d = D[i];
-    long long cur = (long long)((r << 16) | (d >> 16));
-    long long qe = (long long)((double)cur * inv);
-    long long rem = cur - qe * nn;
-    while (rem < 0) { qe -= 1; rem += nn; }
-    while (rem >= nn) { qe += 1; rem -= nn; }
-    const unsigned long long qh = (unsigned long long)qe;
-    cur = (rem << 16) | (long long)(d & 0xFFFFu);
-    qe = (long long)((double)cur * inv);
-    rem = cur - qe * nn;
-    while (rem < 0) { qe -= 1; rem += nn; }
-    while (rem >= nn) { qe += 1; rem -= nn; }
-    r = (unsigned long long)rem;
-    D[i] = (unsigned int)((qh << 16) | (unsigned long long)qe);
-  }
-  int t = 66;
-  while (t >= 0 && D[t] == 0) t--;
-  const int b = (t < 0) ? 0 : 32 * t + 32 - __builtin_clz(D[t]);
-  unsigned long long q;
-  int sh;
-  bool up;
-  if (b <= 53) {
-    sh = 0;
-    q = (unsigned long long)D[0] | ((unsigned long long)D[1] << 32);
-    up = (2 * r > n) || (2 * r == n && (q & 1));
-  } else {
-    sh = b - 53;
-    const int w = sh >> 5, o = sh & 31;
-    q = ((unsigned long long)D[w] | ((unsigned long long)D[w + 1] << 32)) >> o;
-    if (o) q |= (unsigned long long)D[w + 2] << (64 - o);
-    q &= (1ull << 53) - 1;
-    const int rpos = sh - 1;
-    const unsigned int rbit = (D[rpos >> 5] >> (rpos & 31)) & 1u;
-    unsigned int sticky = D[rpos >> 5] & ((1u << (rpos & 31)) - 1u);
-    for (int i = 0; i < (rpos >> 5); i++) sticky |= D[i];
-    up = rbit && (sticky || r != 0 || (q & 1));
-  }
-  if (up) q += 1;
-  if (q == 0) return 0;                               // rounds to zero -> +0
-  if (q < (1ull << 52)) return sign | q;              // denormal
-  if (q == (1ull << 53)) {
-    q = 1ull << 52;
-    sh += 1;
-  }
-  const unsigned long long E = (unsigned long long)sh + 1;
-  if (E >= 2047) return sign | 0x7FF0000000000000ull;
-  return sign | (E << 52) | (q - (1ull << 52));
-}
-
 // ---- wave-parallel carry propagation and rounding -------------------------
 
 __device__ __forceinline__ unsigned int readlane_u32(unsigned int v, int lane) {
@@ -370,42 +242,74 @@ __device__ __forceinline__ void carry_step_regs(long long &A, long long &B, int 
   else B = 0;
 }
 
-// Round sum c[i] 2^(32i-1075) (67 int64 chunks in LDS, |c[i]| < 2^62) to
-// format F, ties to even; specials take precedence.  Called by one whole
-// wavefront (all 64 lanes active); returns the same bits in every lane.  Two
-// parallel carry steps leave every digit below the top in [-1, 2^32]; in
-// the rare case that a digit sits exactly on a bound the serial routine
-// finishes the job (lane 0, D = 70 words of scratch).
-template <class F>
-__device__ inline unsigned long long round_chunks_wave(const long long *c, unsigned long long pos_inf,
-                                                       unsigned long long neg_inf, unsigned long long nan_bits,
-                                                       unsigned int *D, int lane) {
-  bool has;
-  const unsigned long long sp = special_result<F>(pos_inf, neg_inf, nan_bits, &has);
-  if (has) return sp;
+// Exact carry resolution on a wavefront.  After two parallel carry steps
+// every digit below the top is in [-1, 2^32], so the carry out of a digit
+// is -1, 0 or +1 and depends only on the digit and its carry in: a map from
+// {-1, 0, 1} to itself, packed as f(c) + 1 in bits 2(c+1) .. 2(c+1)+1.
+// A digit in [1, 2^32 - 2] absorbs any carry; 0 passes a -1 on; 2^32 - 1
+// passes a +1 on; -1 sends -1 unless it receives +1; 2^32 sends +1 unless
+// it receives -1.  An inclusive scan of map compositions across the lanes
+// (six shuffles) gives every digit its carry in.
+__device__ __forceinline__ unsigned int carry_map(long long d) {
+  if (d == -1) return 0u | (0u << 2) | (1u << 4);
+  if (d == 0) return 0u | (1u << 2) | (1u << 4);
+  if (d == 0xFFFFFFFFll) return 1u | (1u << 2) | (2u << 4);
+  if (d == 0x100000000ll) return 1u | (2u << 2) | (2u << 4);
+  return 1u | (1u << 2) | (1u << 4);
+}
+__device__ __forceinline__ int carry_apply(unsigned int f, int c) { return (int)((f >> (2 * (c + 1))) & 3u) - 1; }
+// g after f
+__device__ __forceinline__ unsigned int carry_compose(unsigned int g, unsigned int f) {
+  unsigned int h = 0;
+#pragma unroll
+  for (int k = 0; k < 3; k++) h |= ((g >> (2 * ((f >> (2 * k)) & 3u))) & 3u) << (2 * k);
+  return h;
+}
+
+// The magnitude of X = sum c[i] 2^(32i) (67 int64 chunks in LDS,
+// |c[i]| < 2^62) held across one wavefront: digit i in lane i (dA, i < 64),
+// digit 64 + j in lane j (dB, j < 2), digit 66 in every lane (mtop, >= 0),
+// every digit below the top in [0, 2^32).  Called by the whole wavefront.
+struct WaveMag {
+  unsigned int dA;
+  unsigned int dB;
+  long long mtop;
+  unsigned long long mA, mB;        // ballots of the nonzero dA / dB
+  unsigned long long neg;           // 1 if X < 0
+  int t;                            // index of the top nonzero digit, -1 if X == 0
+};
+
+__device__ inline WaveMag wave_magnitude(const long long *c, int lane) {
+  WaveMag m;
   long long A = c[lane];
   long long B = (lane < 3) ? c[64 + lane] : 0;
   carry_step_regs(A, B, lane);
   carry_step_regs(A, B, lane);
-  // digits 0..65 now in [-1, 2^32]; a digit on either bound would need a
-  // longer carry chain
-  const bool edgeA = (A < 0) || (A > 0xFFFFFFFFll);
-  const bool edgeB = (lane < 2) && ((B < 0) || (B > 0xFFFFFFFFll));
-  if (__ballot(edgeA || edgeB) != 0ull) {
-    unsigned long long r = 0;
-    if (lane == 0) r = round_chunks<F>(c, 0ull, 0ull, 0ull, D);
-    return readlane_u64(r, 0);
+  // carries in of digits 0..63 by a scan of carry maps
+  unsigned int F = carry_map(A);
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const unsigned int below = (unsigned int)__shfl_up((int)F, off, 64);
+    if (lane >= off) F = carry_compose(F, below);
   }
-  const long long top = (long long)readlane_u64((unsigned long long)B, 2);
-  unsigned int dA = (unsigned int)A;            // digits 0..63
-  unsigned int dB = (lane < 2) ? (unsigned int)B : 0u;  // digits 64, 65
+  const unsigned int Fprev = (unsigned int)__shfl_up((int)F, 1, 64);
+  const int cin = (lane == 0) ? 0 : carry_apply(Fprev, 0);
+  unsigned int dA = (unsigned int)(A + cin);
+  // digits 64, 65 and the top take the remaining carries in order
+  long long cy = carry_apply((unsigned int)__builtin_amdgcn_readlane((int)F, 63), 0);
+  const long long v64 = (long long)readlane_u64((unsigned long long)B, 0) + cy;
+  cy = v64 >> 32;
+  const long long v65 = (long long)readlane_u64((unsigned long long)B, 1) + cy;
+  cy = v65 >> 32;
+  const long long top = (long long)readlane_u64((unsigned long long)B, 2) + cy;
+  unsigned int dB = (lane == 0) ? (unsigned int)v64 : (lane == 1 ? (unsigned int)v65 : 0u);
   long long mtop = top;
-  unsigned long long sign = 0;
+  m.neg = 0;
   if (top < 0) {
     // two's-complement negation: digits below the lowest nonzero one stay 0,
     // that digit becomes 2^32 - d, the digits above are complemented, and the
     // top becomes -top - 1 (or -top if every lower digit is zero)
-    sign = 1ull << F::SIGN;
+    m.neg = 1;
     const unsigned long long nzA = __ballot(dA != 0u);
     const unsigned long long nzB = __ballot(lane < 2 && dB != 0u);
     int k;
@@ -417,42 +321,137 @@ __device__ inline unsigned long long round_chunks_wave(const long long *c, unsig
     if (lane < 2) dB = (iB < k) ? 0u : (iB == k ? 0u - dB : ~dB);
     mtop = (k == 66) ? -top : -top - 1;
   }
-  // magnitude digits: dA (0..63), dB (64, 65), mtop (66, small, >= 0)
-  const unsigned long long mA = __ballot(dA != 0u);
-  const unsigned long long mB = __ballot(lane < 2 && dB != 0u);
-  int t;
-  if (mtop != 0) t = 66;
-  else if (mB) t = 64 + (63 - __clzll((long long)mB));
-  else if (mA) t = 63 - __clzll((long long)mA);
-  else return 0;                                   // exact zero -> +0.0
-  auto digit = [&](int i) -> unsigned int {
-    if (i < 0) return 0u;
-    if (i < 64) return readlane_u32(dA, i);
-    if (i < 66) return readlane_u32(dB, i - 64);
-    if (i == 66) return (unsigned int)mtop;
-    return 0u;
-  };
-  const unsigned int Dt = digit(t);
-  const int Bl = 32 * t + 32 - __clz(Dt);          // bit length of X (units 2^-1075)
+  m.dA = dA;
+  m.dB = dB;
+  m.mtop = mtop;
+  m.mA = __ballot(dA != 0u);
+  m.mB = __ballot(lane < 2 && dB != 0u);
+  if (mtop != 0) m.t = 66;
+  else if (m.mB) m.t = 64 + (63 - __clzll((long long)m.mB));
+  else if (m.mA) m.t = 63 - __clzll((long long)m.mA);
+  else m.t = -1;
+  return m;
+}
+
+// Digit i (uniform i) of the magnitude.
+__device__ __forceinline__ unsigned int wave_digit(const WaveMag &m, int i) {
+  if (i < 0) return 0u;
+  if (i < 64) return readlane_u32(m.dA, i);
+  if (i < 66) return readlane_u32(m.dB, i - 64);
+  if (i == 66) return (unsigned int)m.mtop;
+  return 0u;
+}
+
+// 32 bits of the magnitude from bit position pos up (uniform pos >= 0).
+__device__ __forceinline__ unsigned int wave_bits32(const WaveMag &m, int pos) {
+  const int w = pos >> 5, o = pos & 31;
+  const unsigned int lo = wave_digit(m, w);
+  return o ? ((lo >> o) | (wave_digit(m, w + 1) << (32 - o))) : lo;
+}
+
+// Whether any bit of the magnitude below bit position pos (0 <= pos <
+// 32 * 67) is set.
+__device__ __forceinline__ bool wave_any_below(const WaveMag &m, int pos) {
+  const int rw = pos >> 5;
+  if ((wave_digit(m, rw) & ((1u << (pos & 31)) - 1u)) != 0u) return true;
+  const unsigned long long belowA = (rw >= 64) ? m.mA : (rw > 0 ? (m.mA & ((1ull << rw) - 1ull)) : 0ull);
+  const unsigned long long belowB = (rw > 64) ? (m.mB & ((1ull << (rw - 64)) - 1ull)) : 0ull;
+  return belowA != 0ull || belowB != 0ull;
+}
+
+// Round sum c[i] 2^(32i-1075) (67 int64 chunks in LDS, |c[i]| < 2^62) to
+// format F, ties to even; specials take precedence (Small: obtaining the
+// correctly rounded result).  Called by one whole wavefront (all 64 lanes
+// active); returns the same bits in every lane.
+template <class F>
+__device__ inline unsigned long long round_chunks_wave(const long long *c, unsigned long long pos_inf,
+                                                       unsigned long long neg_inf, unsigned long long nan_bits,
+                                                       int lane) {
+  bool has;
+  const unsigned long long sp = special_result<F>(pos_inf, neg_inf, nan_bits, &has);
+  if (has) return sp;
+  const WaveMag m = wave_magnitude(c, lane);
+  if (m.t < 0) return 0;                           // exact zero -> +0.0
+  const int Bl = 32 * m.t + 32 - __clz(wave_digit(m, m.t));   // bit length of X (units 2^-1075)
   int sh = Bl - F::P;
   if (sh < F::U) sh = F::U;
-  const int w = sh >> 5, o = sh & 31;
-  unsigned long long q = ((unsigned long long)digit(w) | ((unsigned long long)digit(w + 1) << 32)) >> o;
-  if (o) q |= (unsigned long long)digit(w + 2) << (64 - o);
+  unsigned long long q = (unsigned long long)wave_bits32(m, sh) | ((unsigned long long)wave_bits32(m, sh + 32) << 32);
   q &= (1ull << F::P) - 1;
   const int rpos = sh - 1;
-  const int rw = rpos >> 5;
-  const unsigned int rd = digit(rw);
-  const unsigned int rbit = (rd >> (rpos & 31)) & 1u;
-  bool sticky = (rd & ((1u << (rpos & 31)) - 1u)) != 0u;
-  // any nonzero digit strictly below rw
-  const unsigned long long belowA = (rw >= 64) ? mA : (rw > 0 ? (mA & ((1ull << rw) - 1ull)) : 0ull);
-  const unsigned long long belowB = (rw > 64) ? (mB & ((1ull << (rw - 64)) - 1ull)) : 0ull;
-  sticky = sticky || belowA || belowB;
+  const unsigned int rbit = (wave_digit(m, rpos >> 5) >> (rpos & 31)) & 1u;
+  const bool sticky = wave_any_below(m, rpos);
   if (rbit && (sticky || (q & 1))) q += 1;
   unsigned long long bits = ((unsigned long long)(sh - F::U) << (F::P - 1)) + q;
   if ((bits >> (F::P - 1)) >= F::EMAX) bits = F::EMAX << (F::P - 1);
-  return sign | bits;
+  return (m.neg << F::SIGN) | bits;
+}
+
+// The exact mean: the value sum c[i] 2^(32i-1075) divided by n >= 1,
+// rounded once to binary64, ties to even (Discussion, on a correctly rounded
+// mean); a mean that rounds to zero is +0.  Called by one whole wavefront.
+// With A = X/2 in units of 2^-1074, Q = floor(A/n) and R = A mod n (the
+// quotient is rounded on its 53 top bits, the bit below and the sticky OR
+// of the rest and R), only Q's top bits matter: for j >= 0, floor(Q / 2^j) = floor(floor(A / 2^j) / n), and
+// (Q mod 2^j, R) are both zero exactly when A mod (n 2^j) is, i.e. when the
+// low j bits of A and floor(A / 2^j) mod n are.  j is chosen so that
+// floor(A / 2^j) has at most 96 bits and its quotient at least 55, which
+// leaves room for the 53 kept bits and the round bit.
+__device__ inline unsigned long long round_mean_wave(const long long *c, unsigned long long pos_inf,
+                                                     unsigned long long neg_inf, unsigned long long nan_bits,
+                                                     unsigned long long n, int lane) {
+  bool has;
+  const unsigned long long sp = special_result<FmtF64>(pos_inf, neg_inf, nan_bits, &has);
+  if (has) return sp;
+  const WaveMag m = wave_magnitude(c, lane);
+  if (m.t < 0) return 0;                           // exact zero -> +0.0
+  const int bA = 32 * m.t + 31 - __clz(wave_digit(m, m.t));   // bit length of A = X / 2
+  const int bn = 64 - __clzll((long long)n);
+  const int j0 = (bA - bn - 55 > 0) ? bA - bn - 55 : 0;
+  // A' = floor(A / 2^j0) = X >> (j0 + 1), below 2^96
+  const unsigned int a0 = wave_bits32(m, j0 + 1), a1 = wave_bits32(m, j0 + 33), a2 = wave_bits32(m, j0 + 65);
+  const unsigned int aw[3] = {a0, a1, a2};
+  const long long nn = (long long)n;
+  const double inv = 1.0 / (double)n;
+  long long r = 0;
+  unsigned long long T = 0;
+#pragma unroll
+  for (int k = 5; k >= 0; k--) {
+    const long long cur = (r << 16) | (long long)((aw[k >> 1] >> (16 * (k & 1))) & 0xFFFFu);
+    long long qe = (long long)((double)cur * inv);
+    long long rem = cur - qe * nn;
+    while (rem < 0) { qe -= 1; rem += nn; }
+    while (rem >= nn) { qe += 1; rem -= nn; }
+    r = rem;
+    T = (T << 16) | (unsigned long long)qe;
+  }
+  const bool low = (j0 > 0) && wave_any_below(m, j0 + 1);   // bits of A below j0
+  const int bT = T ? 64 - __clzll((long long)T) : 0;
+  unsigned long long q;
+  int sh;
+  bool up;
+  if (j0 == 0 && bT <= 53) {
+    sh = 0;
+    q = T;
+    up = (2 * r > nn) || (2 * r == nn && (q & 1));
+  } else {
+    const int s2 = bT - 53;                        // >= 1
+    q = T >> s2;
+    const bool rb = (T >> (s2 - 1)) & 1ull;
+    const bool sticky = (T & ((1ull << (s2 - 1)) - 1ull)) != 0ull || r != 0 || low;
+    up = rb && (sticky || (q & 1));
+    sh = j0 + s2;
+  }
+  if (up) q += 1;
+  const unsigned long long sign = m.neg << 63;
+  if (q == 0) return 0;                            // rounds to zero -> +0
+  if (q < (1ull << 52)) return sign | q;           // denormal
+  if (q == (1ull << 53)) {
+    q = 1ull << 52;
+    sh += 1;
+  }
+  const unsigned long long E = (unsigned long long)sh + 1;
+  if (E >= 2047) return sign | 0x7FF0000000000000ull;
+  return sign | (E << 52) | (q - (1ull << 52));
 }
 
 }  // namespace exsum

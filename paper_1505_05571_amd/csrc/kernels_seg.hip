@@ -112,7 +112,7 @@ __global__ __launch_bounds__(BLOCK) void seg_long_kernel(const double *__restric
         expected = (unsigned int)(wg_of(s1 - 1 - o0, N, G) - w1 + 1);
         g = &accs[w1];
       }
-      merge_and_round(S.L.small, S.L.spec, &S.L.ticket, S.L.D, g, expected, &out[i + k]);
+      merge_and_round(S.L.small, S.L.spec, &S.L.ticket, g, expected, &out[i + k]);
       if (tid < 68) S.L.small[tid] = 0;
       if (tid < 3) S.L.spec[tid] = 0ull;
       __syncthreads();
@@ -129,7 +129,6 @@ template <int NW>
 struct ShortShared {
   long long acc[NW][small_acc_words<kShortCopies>()];
   unsigned long long spec[NW][4];
-  unsigned int D[NW][70];
 };
 
 // Short segments, one wavefront each.  Offsets are read 64 at a time into
@@ -144,7 +143,6 @@ __global__ __launch_bounds__(BLOCK) void seg_short_kernel(const double *__restri
   const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);   // all lanes active here
   long long *acc = S.acc[wave];
   unsigned long long *spec = S.spec[wave];
-  unsigned int *D = S.D[wave];
   const long long W = (long long)gridDim.x * NW;
   const long long v = (long long)blockIdx.x * NW + wave;
   const long long i1 = nseg * (v + 1) / W;
@@ -159,7 +157,7 @@ __global__ __launch_bounds__(BLOCK) void seg_short_kernel(const double *__restri
       if (s1 - s0 > small_max) continue;               // long: the other kernel's
       small_wave_zero<kShortCopies>(acc, spec, lane);
       small_wave_accumulate<kShortCopies>(acc, spec, SrcF64{x}, s0, s1, lane);
-      wave_merge_and_round(acc, spec, D, nullptr, 1u, &out[i0 + k], lane);
+      wave_merge_and_round(acc, spec, nullptr, 1u, &out[i0 + k], lane);
     }
   }
 }

@@ -25,7 +25,6 @@ struct PieceShared {
   LargeShared L;
   long long wacc[NW][small_acc_words<kPieceCopies>()];
   unsigned long long wspec[NW][4];
-  unsigned int wD[NW][70];
 };
 
 template <int BLOCK, int VEC, int DEPTH>
@@ -42,13 +41,12 @@ __global__ __launch_bounds__(BLOCK) void piece_kernel(const Piece *__restrict__ 
   {
     long long *acc = S.wacc[wave];
     unsigned long long *spec = S.wspec[wave];
-    unsigned int *D = S.wD[wave];
     for (int p = (int)blockIdx.x * NW + wave; p < nshort; p += (int)gridDim.x * NW) {
       const Piece pc = P[p];
       small_wave_zero<kPieceCopies>(acc, spec, lane);
       small_wave_accumulate<kPieceCopies>(acc, spec, SrcF64{pc.x}, 0, pc.n, lane);
       GlobalAcc *g = pc.expected == 1u ? nullptr : &slots[pc.slot];
-      wave_merge_and_round(acc, spec, D, g, pc.expected, pc.out, lane);
+      wave_merge_and_round(acc, spec, g, pc.expected, pc.out, lane);
     }
   }
   __syncthreads();
@@ -60,7 +58,7 @@ __global__ __launch_bounds__(BLOCK) void piece_kernel(const Piece *__restrict__ 
     accumulate_range<BLOCK, VEC, DEPTH, kCarryMode>(S.L, SrcF64{pc.x}, 0, pc.n, precombine, tile);
     final_flush<BLOCK, true, kCarryMode>(S.L);
     GlobalAcc *g = pc.expected == 1u ? nullptr : &slots[pc.slot];
-    merge_and_round(S.L.small, S.L.spec, &S.L.ticket, S.L.D, g, pc.expected, pc.out);
+    merge_and_round(S.L.small, S.L.spec, &S.L.ticket, g, pc.expected, pc.out);
     if (tid < 68) S.L.small[tid] = 0;
     if (tid < 3) S.L.spec[tid] = 0ull;
     __syncthreads();

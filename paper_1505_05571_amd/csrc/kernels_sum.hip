@@ -28,7 +28,7 @@ __global__ __launch_bounds__(BLOCK) void large_kernel(Src src, long long n, Merg
   unsigned int tile = 0;
   accumulate_range<BLOCK, VEC, DEPTH, MODE>(S, src, r0, r1, precombine, tile);
   final_flush<BLOCK, false, MODE>(S);
-  merge_rows_and_finish(S.small, S.spec, S.bcast, S.D, M, fin);
+  merge_rows_and_finish(S.small, S.spec, S.bcast, M, fin);
 }
 
 // Small-only kernel: every wavefront sums a contiguous part into its own
@@ -41,7 +41,6 @@ __global__ __launch_bounds__(BLOCK) void small_kernel(Src src, long long n, Merg
   __shared__ long long s_tot[68];
   __shared__ unsigned long long s_spec[3];
   __shared__ unsigned int s_flag[2];
-  __shared__ unsigned int s_D[70];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int i = tid; i < NW * small_acc_words<1>(); i += BLOCK) (&s_acc[0][0])[i] = 0;
   if (tid < 3) s_spec[tid] = 0ull;
@@ -58,7 +57,7 @@ __global__ __launch_bounds__(BLOCK) void small_kernel(Src src, long long n, Merg
     for (int w = 0; w < NW; w++) t += s_acc[w][tid];
     s_tot[tid] = t;
   }
-  merge_rows_and_finish(s_tot, s_spec, s_flag, s_D, M, fin);
+  merge_rows_and_finish(s_tot, s_spec, s_flag, M, fin);
 }
 
 // The streaming accumulator's own kernels (one wavefront each).
@@ -85,13 +84,12 @@ __global__ __launch_bounds__(64) void acc_merge_kernel(GlobalAcc *dst, const Glo
 
 __global__ __launch_bounds__(64) void acc_round_kernel(const GlobalAcc *acc, double *out) {
   __shared__ long long c[68];
-  __shared__ unsigned int D[70];
   const int lane = threadIdx.x;
   c[lane] = (long long)acc->chunk[lane];
   if (lane < 4) c[64 + lane] = (long long)acc->chunk[64 + lane];
   __builtin_amdgcn_wave_barrier();
   const unsigned long long r =
-      round_chunks_wave<FmtF64>(c, acc->pos_inf, acc->neg_inf, acc->nan_bits, D, lane);
+      round_chunks_wave<FmtF64>(c, acc->pos_inf, acc->neg_inf, acc->nan_bits, lane);
   if (lane == 0) out[0] = __longlong_as_double((long long)r);
 }
 
@@ -215,44 +213,48 @@ hipError_t launch_small(const double *x, int64_t n, MergeRows *M, double *out, h
 // default variant (1024 threads, 4 positions per thread per tile, 2 tiles in
 // flight, carry-triggered transfers).
 namespace {
-template <class Src, class Fin>
+template <int BLOCK, int VEC, class Src, class Fin>
 hipError_t launch_op(const Src &src, int64_t n, const Fin &fin, MergeRows *M, hipStream_t s, int grid, bool small,
                      int precombine) {
   if (grid < 1) grid = 1;
   if (small)
     hipLaunchKernelGGL((small_kernel<256, Src, Fin>), dim3(grid), dim3(256), 0, s, src, (long long)n, M, fin);
   else
-    hipLaunchKernelGGL((large_kernel<kOpBlock, 4, 2, kCarryMode, Src, Fin>), dim3(grid), dim3(kOpBlock), 0, s, src,
+    hipLaunchKernelGGL((large_kernel<BLOCK, VEC, 2, kCarryMode, Src, Fin>), dim3(grid), dim3(BLOCK), 0, s, src,
                        (long long)n, M, fin, precombine);
   return hipGetLastError();
 }
+// Sources with more registers per position use shapes that fit their
+// registers without spilling (measured best of 512x4 and 1024x2 for each).
+constexpr int kDotBlock = 512, kDotVec = 4;      // two inputs per position
+constexpr int kF32Block = 1024, kF32Vec = 2;     // four terms per position
 }  // namespace
 
 hipError_t launch_sqnorm(const double *x, int64_t n, double *out, MergeRows *M, hipStream_t s, int grid, bool small,
                          int precombine) {
-  return launch_op(SrcSq{{x}}, n, FinF64{out}, M, s, grid, small, precombine);
+  return launch_op<kOpBlock, 4>(SrcSq{{x}}, n, FinF64{out}, M, s, grid, small, precombine);
 }
 
 hipError_t launch_dot(const double *x, const double *y, int64_t n, double *out, MergeRows *M, hipStream_t s,
                       int grid, bool small, int precombine) {
   if (((reinterpret_cast<uintptr_t>(x) ^ reinterpret_cast<uintptr_t>(y)) & 15) == 0)
-    return launch_op(SrcDot<true>{x, y}, n, FinF64{out}, M, s, grid, small, precombine);
-  return launch_op(SrcDot<false>{x, y}, n, FinF64{out}, M, s, grid, small, precombine);
+    return launch_op<kDotBlock, kDotVec>(SrcDot<true>{x, y}, n, FinF64{out}, M, s, grid, small, precombine);
+  return launch_op<kDotBlock, kDotVec>(SrcDot<false>{x, y}, n, FinF64{out}, M, s, grid, small, precombine);
 }
 
 hipError_t launch_mean(const double *x, int64_t n, double *out, MergeRows *M, hipStream_t s, int grid, bool small,
                        int precombine) {
-  return launch_op(SrcF64{x}, n, FinMean{out, (unsigned long long)n}, M, s, grid, small, precombine);
+  return launch_op<kOpBlock, 4>(SrcF64{x}, n, FinMean{out, (unsigned long long)n}, M, s, grid, small, precombine);
 }
 
 hipError_t launch_f32(const float *x, int64_t n, float *out, MergeRows *M, hipStream_t s, int grid, bool small,
                       int precombine) {
-  return launch_op(SrcF32{x}, n, FinF32{out}, M, s, grid, small, precombine);
+  return launch_op<kF32Block, kF32Vec>(SrcF32{x}, n, FinF32{out}, M, s, grid, small, precombine);
 }
 
 hipError_t launch_acc_add(const double *x, int64_t n, GlobalAcc *acc, MergeRows *M, hipStream_t s, int grid,
                           bool small, int precombine) {
-  return launch_op(SrcF64{x}, n, FinAcc{acc}, M, s, grid, small, precombine);
+  return launch_op<kOpBlock, 4>(SrcF64{x}, n, FinAcc{acc}, M, s, grid, small, precombine);
 }
 
 hipError_t launch_acc_zero(GlobalAcc *acc, hipStream_t s) {

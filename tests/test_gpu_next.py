@@ -121,6 +121,11 @@ def test_mean(ex):
         [5e-324, 5e-324, 0.0],                   # 2^-1075 * 4/3 rounds to 2^-1074
         [-3.0, 1.0],
         [1.0] * 7 + [2.0 ** -60],
+        [5e-324, 0.0],                           # 2^-1075: a tie between 0 and 2^-1074 -> +0
+        [3 * 5e-324, 0.0],                       # 1.5 units: a tie -> 2 units (even)
+        [1.0 + 2.0 ** -52, 2.0 ** -53, 0.0, 0.0],            # quotient needs its low bits (sticky)
+        [2.0 ** 1000, 2.0 ** 1000 * (1 + 2.0 ** -52), 2.0 ** -1000],   # long quotient, tiny remainder
+        list(np.ldexp(np.arange(1, 12, dtype=np.float64), 900)) + [-(2.0 ** -1070)],
     ]
     for vals in cases:
         x = np.array(vals, dtype=np.float64)
