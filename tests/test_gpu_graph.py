@@ -1,0 +1,68 @@
+"""HIP graph capture of the library calls: after one call on a stream has
+allocated that stream's workspace, exsum_f64, exsum_segmented_f64 and the
+further reductions can be captured on it and replayed; every replay must give
+the oracle's bits, with eager work between replays and with input changed
+between replays (the graph reads the buffers live)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1505_05571_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ex():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1505_05571_amd as ex
+    ex.load_library()
+    return ex
+
+
+def bits(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def test_capture_and_replay(ex):
+    s = torch.cuda.Stream()
+    x1 = W.uniform_exponent(2_000_003, seed=31)
+    x2 = W.uniform_exponent(2_000_003, seed=33)
+    xs, off = W.segments(nseg=3000, seed=32, hi=40000)
+    y = W.uniform_exponent(2_000_003, seed=34, kmin=-200, kmax=200)
+    with torch.cuda.stream(s):
+        xt = torch.from_numpy(x1).to("cuda:0")
+        yt = torch.from_numpy(y).to("cuda:0")
+        xst = torch.from_numpy(xs).to("cuda:0")
+        offt = torch.from_numpy(off).to("cuda:0")
+        out = torch.empty(4, dtype=torch.float64, device="cuda:0")
+        outs = torch.empty(off.size - 1, dtype=torch.float64, device="cuda:0")
+        # first calls on this stream: allocate its workspace outside the capture
+        ex.exsum_f64(xt, out=out[0:1], stream=s)
+        ex.exsum_segmented_f64(xst, offt, out=outs, stream=s)
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        ex.exsum_f64(xt, out=out[0:1], stream=s)
+        ex.exsum_segmented_f64(xst, offt, out=outs, stream=s)
+        ex.exsum_dot_f64(xt, yt, out=out[1:2], stream=s)
+        ex.exsum_mean_f64(xt, out=out[2:3], stream=s)
+    want_seg = oracle.segmented_f64(xs, off)
+    for rep in range(4):
+        xv = x1 if rep % 2 == 0 else x2
+        # eager work between replays: new input, poisoned outputs, another sum
+        xt.copy_(torch.from_numpy(xv))
+        out.fill_(float("nan"))
+        outs.fill_(float("nan"))
+        ex.exsum_f64(yt, out=out[3:4])
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = bits(out)
+        assert got[0] == int(oracle.sum_f64(xv)), rep
+        assert got[1] == int(oracle.dot_f64(xv, y)), rep
+        assert got[2] == int(oracle.mean_f64(xv)), rep
+        assert got[3] == int(oracle.sum_f64(y)), rep
+        assert np.array_equal(bits(outs), want_seg), rep
