@@ -237,8 +237,8 @@ int exsum_acc_round_f64(const void *acc, double *out, void *stream);
  * A server is used from one host thread at a time.
  * ------------------------------------------------------------------------ */
 typedef struct {
-    int64_t step_terms;    /* term budget of one step, >= piece_terms (default 2^26) */
-    int64_t piece_terms;   /* most terms in one piece, >= 1 (default 2^17) */
+    int64_t step_terms;    /* term budget of one step, >= piece_terms (default 2^27) */
+    int64_t piece_terms;   /* most terms in one piece, >= 1 (default 2^16) */
     int64_t short_max;     /* pieces of at most this many terms are summed by one
                               wavefront, the others by one workgroup (default 4096) */
     int32_t max_slots;     /* requests cut into pieces that may be active at once,

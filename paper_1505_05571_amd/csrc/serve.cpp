@@ -22,8 +22,8 @@ constexpr int64_t kMaxTerms = int64_t(1) << 40;
 
 exsum_server_config default_server_config() {
   exsum_server_config c;
-  c.step_terms = int64_t(1) << 26;
-  c.piece_terms = int64_t(1) << 17;
+  c.step_terms = int64_t(1) << 27;
+  c.piece_terms = int64_t(1) << 16;
   c.short_max = 4096;
   c.max_slots = 4096;
   c.max_pieces = 16384;
