@@ -86,13 +86,13 @@ int get_workspace(hipStream_t s, Workspace **out, int *dev_out) {
     Workspace w;
     w.max_grid = kMaxGrid;
     void *p = nullptr;
-    const size_t mb = (merge_rows_bytes() + 255) / 256 * 256;
+    const size_t mb = (global_acc_bytes() + 255) / 256 * 256;
     const size_t bytes = mb + sizeof(double) * kMaxGrid + 256;
     e = hipMalloc(&p, bytes);
     if (e != hipSuccess) return status_of(e);
     e = hipMemset(p, 0, bytes);
     if (e != hipSuccess) { (void)hipFree(p); return status_of(e); }
-    w.rows = reinterpret_cast<MergeRows *>(p);
+    w.acc = reinterpret_cast<GlobalAcc *>(p);
     w.partials = reinterpret_cast<double *>(static_cast<char *>(p) + mb);
     w.ticket = reinterpret_cast<unsigned int *>(static_cast<char *>(p) + mb + sizeof(double) * kMaxGrid);
     it = g_ws.emplace(key, w).first;
@@ -113,7 +113,7 @@ int run_sum(const double *x, int64_t n, double *out, hipStream_t s, const exsum_
   if (n <= c.small_max) {
     int grid = c.small_grid;
     if (grid == 0) grid = (int)std::min<int64_t>(std::max<int64_t>((n + 8191) / 8192, 1), 64);
-    e = launch_small(x, n, w->rows, out, s, grid);
+    e = launch_small(x, n, w->acc, out, s, grid);
   } else {
     int grid = c.large_grid;
     if (grid == 0) {
@@ -122,7 +122,7 @@ int run_sum(const double *x, int64_t n, double *out, hipStream_t s, const exsum_
       const int64_t want = (n + 4 * tile_terms - 1) / (4 * tile_terms);
       grid = (int)std::min<int64_t>(std::max<int64_t>(want, 1), int64_t(cu_count(dev)));
     }
-    e = launch_large(x, n, w->rows, out, s, c.large_block, c.large_vec, c.large_depth, c.large_mode, grid,
+    e = launch_large(x, n, w->acc, out, s, c.large_block, c.large_vec, c.large_depth, c.large_mode, grid,
                      c.precombine);
   }
   return status_of(e);
@@ -252,7 +252,7 @@ int exsum_sqnorm_f64(const double *x, int64_t n, double *out, void *stream) {
   int st = op_setup(s, &c, &w, &dev);
   if (st != EXSUM_OK) return st;
   const OpPlan p = plan_op(n, 2, c, dev);
-  return status_of(launch_sqnorm(x, n, out, w->rows, s, p.grid, p.small, c.precombine));
+  return status_of(launch_sqnorm(x, n, out, w->acc, s, p.grid, p.small, c.precombine));
 }
 
 int exsum_dot_f64(const double *x, const double *y, int64_t n, double *out, void *stream) {
@@ -264,7 +264,7 @@ int exsum_dot_f64(const double *x, const double *y, int64_t n, double *out, void
   int st = op_setup(s, &c, &w, &dev);
   if (st != EXSUM_OK) return st;
   const OpPlan p = plan_op(n, 2, c, dev);
-  return status_of(launch_dot(x, y, n, out, w->rows, s, p.grid, p.small, c.precombine));
+  return status_of(launch_dot(x, y, n, out, w->acc, s, p.grid, p.small, c.precombine));
 }
 
 int exsum_mean_f64(const double *x, int64_t n, double *out, void *stream) {
@@ -276,7 +276,7 @@ int exsum_mean_f64(const double *x, int64_t n, double *out, void *stream) {
   int st = op_setup(s, &c, &w, &dev);
   if (st != EXSUM_OK) return st;
   const OpPlan p = plan_op(n, 2, c, dev);
-  return status_of(launch_mean(x, n, out, w->rows, s, p.grid, p.small, c.precombine));
+  return status_of(launch_mean(x, n, out, w->acc, s, p.grid, p.small, c.precombine));
 }
 
 int exsum_f32(const float *x, int64_t n, float *out, void *stream) {
@@ -288,7 +288,7 @@ int exsum_f32(const float *x, int64_t n, float *out, void *stream) {
   int st = op_setup(s, &c, &w, &dev);
   if (st != EXSUM_OK) return st;
   const OpPlan p = plan_op(n, 4, c, dev);
-  return status_of(launch_f32(x, n, out, w->rows, s, p.grid, p.small, c.precombine));
+  return status_of(launch_f32(x, n, out, w->acc, s, p.grid, p.small, c.precombine));
 }
 
 int exsum_acc_zero(void *acc, void *stream) {
@@ -306,7 +306,7 @@ int exsum_acc_add_f64(void *acc, const double *x, int64_t n, void *stream) {
   int st = op_setup(s, &c, &w, &dev);
   if (st != EXSUM_OK) return st;
   const OpPlan p = plan_op(n, 2, c, dev);
-  return status_of(launch_acc_add(x, n, static_cast<GlobalAcc *>(acc), w->rows, s, p.grid, p.small, c.precombine));
+  return status_of(launch_acc_add(x, n, static_cast<GlobalAcc *>(acc), w->acc, s, p.grid, p.small, c.precombine));
 }
 
 int exsum_acc_merge(void *dst, const void *src, void *stream) {
@@ -341,7 +341,7 @@ int exsum_release(void) {
     int cur = 0;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(kv.first.first);
-    hipError_t e = hipFree(kv.second.rows);
+    hipError_t e = hipFree(kv.second.acc);
     if (first == hipSuccess) first = e;
     if (kv.second.seg_accs) {
       e = hipFree(kv.second.seg_accs);

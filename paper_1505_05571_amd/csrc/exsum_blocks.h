@@ -681,77 +681,46 @@ __device__ __forceinline__ void wave_merge_and_round(long long *acc, unsigned lo
   if (lane == 0) out[0] = __longlong_as_double((long long)r);
 }
 
-// Merge by rows (used by the one-sum kernels, where every workgroup of the
-// grid takes part, so a shared accumulator would see heavy atomic
-// contention).  Each workgroup stores its small accumulator as a row; groups
-// of kMergeGroup rows are summed by the group's last arrival and the group
-// sums by the last group, which applies the finisher to the total.  Returns
-// true in that workgroup.  Called by every thread (block of at least 128
-// threads).
-// Combine word w of rows [r0, r0+nr) of a row array: chunk words add, the
-// infinity flags OR, the NaN word takes the unsigned maximum.  Sixteen loads
-// are in flight at a time.
-template <int KIND>
-__device__ __forceinline__ long long combine_rows_kind(const long long (*rows)[kRowWords], unsigned int r0,
-                                                       unsigned int nr, int w) {
-  long long acc = 0;
-  for (unsigned int base = 0; base < nr; base += 16) {
-    long long v[16];
-#pragma unroll
-    for (int k = 0; k < 16; k++) v[k] = (base + k < nr) ? coherent_load(&rows[r0 + base + k][w]) : 0;
-#pragma unroll
-    for (int k = 0; k < 16; k++) {
-      if (KIND == 0) acc += v[k];
-      else if (KIND == 1) acc |= v[k];
-      else acc = ((unsigned long long)v[k] > (unsigned long long)acc) ? v[k] : acc;
-    }
-  }
-  return acc;
-}
-
-__device__ __forceinline__ long long combine_rows(const long long (*rows)[kRowWords], unsigned int r0,
-                                                  unsigned int nr, int w) {
-  if (w < 68) return combine_rows_kind<0>(rows, r0, nr, w);
-  if (w < 70) return combine_rows_kind<1>(rows, r0, nr, w);
-  return combine_rows_kind<2>(rows, r0, nr, w);
-}
-
+// Merge of a whole grid into one accumulator (the one-sum kernels): every
+// workgroup adds its small accumulator into `g` with 64-bit device atomics
+// (exact and order independent), waits for them to complete and takes a
+// ticket; the last one reads and clears `g` with atomic exchanges and
+// applies the finisher (Discussion: add the small superaccumulators of the
+// parts, finish once).  The adds need no fence: the device-scope atomics
+// and the wait for this thread's memory operations order them before the
+// ticket.  Returns true in the finishing workgroup.  Called by every thread
+// (at least 128).
 template <class Fin>
-__device__ __forceinline__ bool merge_rows_and_finish(long long *s_small, unsigned long long *spec,
-                                                      unsigned int *s_flag, MergeRows *__restrict__ M,
+__device__ __forceinline__ bool merge_grid_and_finish(long long *s_small, unsigned long long *spec,
+                                                      unsigned int *s_ticket, GlobalAcc *__restrict__ g,
                                                       const Fin &fin) {
   const int tid = threadIdx.x;
-  const unsigned int G = gridDim.x, b = blockIdx.x;
+  const unsigned int G = gridDim.x;
   __syncthreads();
   if (G == 1) {
     fin(s_small, spec);
     __syncthreads();
     return true;
   }
-  if (tid < 68) coherent_store(&M->rows[b][tid], (tid < kSChunks) ? s_small[tid] : 0);
-  else if (tid < 71) coherent_store(&M->rows[b][tid], (long long)spec[tid - 68]);
-  wait_memory();
-  __syncthreads();
-  const unsigned int grp = b / kMergeGroup;
-  const unsigned int g0 = grp * kMergeGroup;
-  const unsigned int gsz = (G - g0 < (unsigned int)kMergeGroup) ? G - g0 : (unsigned int)kMergeGroup;
-  const unsigned int ngrp = (G + kMergeGroup - 1) / kMergeGroup;
-  if (tid == 0) s_flag[0] = (ticket_add(&M->gticket[grp]) == gsz - 1u) ? 1u : 0u;
-  __syncthreads();
-  if (!s_flag[0]) return false;
-  if (tid < 71) coherent_store(&M->grows[grp][tid], combine_rows(M->rows, g0, gsz, tid));
-  if (tid == 0) __hip_atomic_store(&M->gticket[grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  wait_memory();
-  __syncthreads();
-  if (tid == 0) s_flag[1] = (ticket_add(&M->ticket) == ngrp - 1u) ? 1u : 0u;
-  __syncthreads();
-  if (!s_flag[1]) return false;
-  if (tid < 71) {
-    const long long acc = combine_rows(M->grows, 0, ngrp, tid);
-    if (tid < 68) s_small[tid] = acc;
-    else spec[tid - 68] = (unsigned long long)acc;
+  if (tid < kSChunks) {
+    const long long v = s_small[tid];
+    if (v) atomicAdd(&g->chunk[tid], (unsigned long long)v);
   }
-  if (tid == 0) __hip_atomic_store(&M->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (tid == 0) {
+    if (spec[0]) atomicOr(&g->pos_inf, 1ull);
+    if (spec[1]) atomicOr(&g->neg_inf, 1ull);
+    if (spec[2]) atomicMax(&g->nan_bits, spec[2]);
+  }
+  wait_memory();
+  __syncthreads();
+  if (tid == 0) *s_ticket = ticket_add(&g->ticket);
+  __syncthreads();
+  if (*s_ticket != G - 1u) return false;
+  if (tid < kSChunks) s_small[tid] = (long long)atomicExch(&g->chunk[tid], 0ull);
+  if (tid == 96) spec[0] = atomicExch(&g->pos_inf, 0ull);
+  if (tid == 97) spec[1] = atomicExch(&g->neg_inf, 0ull);
+  if (tid == 98) spec[2] = atomicExch(&g->nan_bits, 0ull);
+  if (tid == 99) atomicExch(&g->ticket, 0u);
   __syncthreads();
   fin(s_small, spec);
   __syncthreads();

@@ -42,22 +42,6 @@ struct alignas(64) GlobalAcc {
 };
 static_assert(sizeof(GlobalAcc) == 576, "GlobalAcc layout");
 
-// Merge workspace of one multi-workgroup sum.  Each workgroup writes its
-// small accumulator as a row with plain stores; groups of kMergeGroup
-// workgroups are summed by the group's last arrival, and the group sums by
-// the last group to finish.  Only two small counters are atomic, so no
-// address sees more than max(kMergeGroup, groups) atomic updates.  Row
-// layout: words 0..66 chunks, 68 +Inf seen, 69 -Inf seen, 70 max NaN bits.
-constexpr int kMergeGroup = 16;
-constexpr int kRowWords = 72;
-struct MergeRows {
-  long long rows[kMaxGrid][kRowWords];
-  long long grows[kMaxGrid / kMergeGroup][kRowWords];
-  unsigned int gticket[kMaxGrid / kMergeGroup];
-  unsigned int ticket;
-  unsigned int pad[63];
-};
-
 // ---- synchronisation -------------------------------------------------------
 
 // Workgroup barrier that waits only for this wave's LDS traffic.  Global loads

@@ -9,12 +9,11 @@ namespace exsum {
 constexpr int kMaxGrid = 8192;       // most workgroups one single-sum launch may use
 
 struct GlobalAcc;
-struct MergeRows;
 
 // Per-(device, stream) workspace.  Everything the kernels write here is left
 // zeroed when a call completes.
 struct Workspace {
-  MergeRows *rows = nullptr;           // merge workspace of the single-sum kernels
+  GlobalAcc *acc = nullptr;            // merge accumulator of the one-sum kernels
   double *partials = nullptr;          // per-workgroup partials of the inexact sum
   unsigned int *ticket = nullptr;      // ticket of the inexact sum
   int max_grid = 0;                    // capacity of `partials`
@@ -28,10 +27,10 @@ int status_of(hipError_t e);
 int cu_count(int dev);
 
 // Launchers (kernels_sum.hip).  Return a hipError_t.
-hipError_t launch_large(const double *x, int64_t n, MergeRows *M, double *out, hipStream_t s,
+hipError_t launch_large(const double *x, int64_t n, GlobalAcc *M, double *out, hipStream_t s,
                         int block, int vec, int depth, int mode, int grid, int precombine);
 bool large_variant_exists(int block, int vec, int depth, int mode);
-hipError_t launch_small(const double *x, int64_t n, MergeRows *M, double *out, hipStream_t s,
+hipError_t launch_small(const double *x, int64_t n, GlobalAcc *M, double *out, hipStream_t s,
                         int grid);
 hipError_t launch_inexact(const double *x, int64_t n, double *partials, unsigned int *ticket,
                           double *out, hipStream_t s, int grid);
@@ -39,15 +38,15 @@ hipError_t launch_inexact(const double *x, int64_t n, double *partials, unsigned
 // Further sums over the same path (kernels_sum.hip): the small-only kernel
 // when `small`, else the large kernel in its default variant (op_block()
 // threads, 4 positions per thread per tile).
-hipError_t launch_sqnorm(const double *x, int64_t n, double *out, MergeRows *M, hipStream_t s, int grid,
+hipError_t launch_sqnorm(const double *x, int64_t n, double *out, GlobalAcc *M, hipStream_t s, int grid,
                          bool small, int precombine);
-hipError_t launch_dot(const double *x, const double *y, int64_t n, double *out, MergeRows *M, hipStream_t s,
+hipError_t launch_dot(const double *x, const double *y, int64_t n, double *out, GlobalAcc *M, hipStream_t s,
                       int grid, bool small, int precombine);
-hipError_t launch_mean(const double *x, int64_t n, double *out, MergeRows *M, hipStream_t s, int grid, bool small,
+hipError_t launch_mean(const double *x, int64_t n, double *out, GlobalAcc *M, hipStream_t s, int grid, bool small,
                        int precombine);
-hipError_t launch_f32(const float *x, int64_t n, float *out, MergeRows *M, hipStream_t s, int grid, bool small,
+hipError_t launch_f32(const float *x, int64_t n, float *out, GlobalAcc *M, hipStream_t s, int grid, bool small,
                       int precombine);
-hipError_t launch_acc_add(const double *x, int64_t n, GlobalAcc *acc, MergeRows *M, hipStream_t s, int grid,
+hipError_t launch_acc_add(const double *x, int64_t n, GlobalAcc *acc, GlobalAcc *M, hipStream_t s, int grid,
                           bool small, int precombine);
 hipError_t launch_acc_zero(GlobalAcc *acc, hipStream_t s);
 hipError_t launch_acc_merge(GlobalAcc *dst, const GlobalAcc *src, hipStream_t s);
@@ -63,7 +62,6 @@ hipError_t launch_segmented(const double *x, const int64_t *offsets, int64_t nse
                             int precombine);
 int seg_short_waves_per_block();
 
-size_t merge_rows_bytes();
 
 // One piece of a served request (host and device layout).  `expected` is the
 // request's total number of pieces when this piece belongs to the step that

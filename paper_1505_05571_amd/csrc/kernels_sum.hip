@@ -16,7 +16,7 @@ namespace exsum {
 namespace {
 
 template <int BLOCK, int VEC, int DEPTH, int MODE, class Src, class Fin>
-__global__ __launch_bounds__(BLOCK) void large_kernel(Src src, long long n, MergeRows *__restrict__ M, Fin fin,
+__global__ __launch_bounds__(BLOCK) void large_kernel(Src src, long long n, GlobalAcc *__restrict__ M, Fin fin,
                                                       int precombine) {
   __shared__ LargeShared S;
   const int tid = threadIdx.x;
@@ -28,14 +28,14 @@ __global__ __launch_bounds__(BLOCK) void large_kernel(Src src, long long n, Merg
   unsigned int tile = 0;
   accumulate_range<BLOCK, VEC, DEPTH, MODE>(S, src, r0, r1, precombine, tile);
   final_flush<BLOCK, false, MODE>(S);
-  merge_rows_and_finish(S.small, S.spec, S.bcast, M, fin);
+  merge_grid_and_finish(S.small, S.spec, &S.ticket, M, fin);
 }
 
 // Small-only kernel: every wavefront sums a contiguous part into its own
 // small superaccumulator; the workgroup adds its wavefronts' accumulators
 // (each below 2^33 per chunk after the final carry step) and merges.
 template <int BLOCK, class Src, class Fin>
-__global__ __launch_bounds__(BLOCK) void small_kernel(Src src, long long n, MergeRows *__restrict__ M, Fin fin) {
+__global__ __launch_bounds__(BLOCK) void small_kernel(Src src, long long n, GlobalAcc *__restrict__ M, Fin fin) {
   constexpr int NW = BLOCK / 64;
   __shared__ long long s_acc[NW][small_acc_words<1>()];
   __shared__ long long s_tot[68];
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(BLOCK) void small_kernel(Src src, long long n, Merg
     for (int w = 0; w < NW; w++) t += s_acc[w][tid];
     s_tot[tid] = t;
   }
-  merge_rows_and_finish(s_tot, s_spec, s_flag, M, fin);
+  merge_grid_and_finish(s_tot, s_spec, s_flag, M, fin);
 }
 
 // The streaming accumulator's own kernels (one wavefront each).
@@ -180,7 +180,7 @@ constexpr int kOpBlock = 1024;
   X(1024, 2, 2, kCarryMode)     \
   X(1024, 4, 2, kCarryMode)
 
-hipError_t launch_large(const double *x, int64_t n, MergeRows *M, double *out, hipStream_t s, int block,
+hipError_t launch_large(const double *x, int64_t n, GlobalAcc *M, double *out, hipStream_t s, int block,
                         int vec, int depth, int mode, int grid, int precombine) {
   if (grid < 1) grid = 1;
 #define EXSUM_LAUNCH(B, V, D, MD)                                                                             \
@@ -202,7 +202,7 @@ bool large_variant_exists(int block, int vec, int depth, int mode) {
   return false;
 }
 
-hipError_t launch_small(const double *x, int64_t n, MergeRows *M, double *out, hipStream_t s, int grid) {
+hipError_t launch_small(const double *x, int64_t n, GlobalAcc *M, double *out, hipStream_t s, int grid) {
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL((small_kernel<256, SrcF64, FinF64>), dim3(grid), dim3(256), 0, s, SrcF64{x}, (long long)n, M,
                      FinF64{out});
@@ -214,7 +214,7 @@ hipError_t launch_small(const double *x, int64_t n, MergeRows *M, double *out, h
 // flight, carry-triggered transfers).
 namespace {
 template <int BLOCK, int VEC, class Src, class Fin>
-hipError_t launch_op(const Src &src, int64_t n, const Fin &fin, MergeRows *M, hipStream_t s, int grid, bool small,
+hipError_t launch_op(const Src &src, int64_t n, const Fin &fin, GlobalAcc *M, hipStream_t s, int grid, bool small,
                      int precombine) {
   if (grid < 1) grid = 1;
   if (small)
@@ -230,29 +230,29 @@ constexpr int kDotBlock = 512, kDotVec = 4;      // two inputs per position
 constexpr int kF32Block = 1024, kF32Vec = 2;     // four terms per position
 }  // namespace
 
-hipError_t launch_sqnorm(const double *x, int64_t n, double *out, MergeRows *M, hipStream_t s, int grid, bool small,
+hipError_t launch_sqnorm(const double *x, int64_t n, double *out, GlobalAcc *M, hipStream_t s, int grid, bool small,
                          int precombine) {
   return launch_op<kOpBlock, 4>(SrcSq{{x}}, n, FinF64{out}, M, s, grid, small, precombine);
 }
 
-hipError_t launch_dot(const double *x, const double *y, int64_t n, double *out, MergeRows *M, hipStream_t s,
+hipError_t launch_dot(const double *x, const double *y, int64_t n, double *out, GlobalAcc *M, hipStream_t s,
                       int grid, bool small, int precombine) {
   if (((reinterpret_cast<uintptr_t>(x) ^ reinterpret_cast<uintptr_t>(y)) & 15) == 0)
     return launch_op<kDotBlock, kDotVec>(SrcDot<true>{x, y}, n, FinF64{out}, M, s, grid, small, precombine);
   return launch_op<kDotBlock, kDotVec>(SrcDot<false>{x, y}, n, FinF64{out}, M, s, grid, small, precombine);
 }
 
-hipError_t launch_mean(const double *x, int64_t n, double *out, MergeRows *M, hipStream_t s, int grid, bool small,
+hipError_t launch_mean(const double *x, int64_t n, double *out, GlobalAcc *M, hipStream_t s, int grid, bool small,
                        int precombine) {
   return launch_op<kOpBlock, 4>(SrcF64{x}, n, FinMean{out, (unsigned long long)n}, M, s, grid, small, precombine);
 }
 
-hipError_t launch_f32(const float *x, int64_t n, float *out, MergeRows *M, hipStream_t s, int grid, bool small,
+hipError_t launch_f32(const float *x, int64_t n, float *out, GlobalAcc *M, hipStream_t s, int grid, bool small,
                       int precombine) {
   return launch_op<kF32Block, kF32Vec>(SrcF32{x}, n, FinF32{out}, M, s, grid, small, precombine);
 }
 
-hipError_t launch_acc_add(const double *x, int64_t n, GlobalAcc *acc, MergeRows *M, hipStream_t s, int grid,
+hipError_t launch_acc_add(const double *x, int64_t n, GlobalAcc *acc, GlobalAcc *M, hipStream_t s, int grid,
                           bool small, int precombine) {
   return launch_op<kOpBlock, 4>(SrcF64{x}, n, FinAcc{acc}, M, s, grid, small, precombine);
 }
@@ -285,5 +285,4 @@ hipError_t launch_inexact(const double *x, int64_t n, double *partials, unsigned
 }  // namespace exsum
 
 namespace exsum {
-size_t merge_rows_bytes() { return sizeof(MergeRows); }
 }  // namespace exsum
