@@ -78,14 +78,17 @@ int exsum_f64(const double *x, int64_t n, double *out, void *stream);
  * for 0 <= i < nseg.
  *
  * Many independent exact sums (same definition as exsum_f64) in two
- * launches on `stream` that write disjoint outputs.  Segments of at most
- * seg_small_max terms (empty ones included) are summed whole, each by one
- * wavefront with a small superaccumulator; longer ones by workgroups with
- * the large superaccumulator, each workgroup taking an equal share of the
- * concatenated terms, and a segment cut by workgroup boundaries is merged
- * from its pieces with integer additions (Performance evaluations: the small
- * method wins for short sums, the large one for long sums; Discussion: parts
- * summed separately are added as small superaccumulators).
+ * launches on `stream` that write disjoint outputs.  Segments longer than
+ * seg_small_max terms are summed first, by workgroups with the large
+ * superaccumulator, each workgroup taking an equal share of the
+ * concatenated terms; a segment cut by workgroup boundaries is merged from
+ * its pieces with integer additions.  Segments of at most seg_small_max
+ * terms (empty ones included) are then summed whole, each by one wavefront
+ * with a small superaccumulator; one workgroup per compute unit takes an
+ * equal share of their total length and hands its segments to its
+ * wavefronts as they come free (Performance evaluations: the small method
+ * wins for short sums, the large one for long sums; Discussion: parts summed
+ * separately are added as small superaccumulators).
  *   x       : terms, device memory.
  *   offsets : nseg+1 int64 values, device memory, non-decreasing;
  *             offsets[0] need not be 0.  Not checked on the device.
@@ -136,6 +139,8 @@ int exsum_inexact_f64(const double *x, int64_t n, double *out, void *stream);
  *   seg_small_max : segments of at most this many terms (0 .. 2^20) are
  *                   summed by one wavefront with the small accumulator
  *                   alone; longer ones by workgroups with the large one.
+ *                   (The short-segment kernel always runs one workgroup
+ *                   per compute unit.)
  */
 typedef struct {
     int32_t large_block;

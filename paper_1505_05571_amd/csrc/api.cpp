@@ -222,24 +222,26 @@ int exsum_segmented_f64(const double *x, const int64_t *offsets, int64_t nseg, d
   int grid = c.seg_grid;
   if (grid == 0) grid = cu_count(dev);
   GlobalAcc *accs = nullptr;
+  long long *chunks = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_mu);
     if (w->seg_accs == nullptr) {
       void *p = nullptr;
-      const size_t bytes = global_acc_bytes() * (size_t)kMaxGrid;
+      const size_t abytes = global_acc_bytes() * (size_t)kMaxGrid;
+      const size_t bytes = abytes + sizeof(long long) * (size_t)kMaxGrid;
       hipError_t e = hipMalloc(&p, bytes);
       if (e != hipSuccess) return status_of(e);
       e = hipMemset(p, 0, bytes);
       if (e != hipSuccess) { (void)hipFree(p); return status_of(e); }
       w->seg_accs = reinterpret_cast<GlobalAcc *>(p);
+      w->seg_chunks = reinterpret_cast<long long *>(static_cast<char *>(p) + abytes);
     }
     accs = w->seg_accs;
+    chunks = w->seg_chunks;
   }
-  // short segments: about 24 wavefronts per compute unit, at most one per segment
-  const int64_t per_block = seg_short_waves_per_block();
-  const int64_t waves = std::min<int64_t>(nseg, int64_t(24) * cu_count(dev));
-  const int short_grid = (int)std::max<int64_t>((waves + per_block - 1) / per_block, 1);
-  return status_of(launch_segmented(x, offsets, nseg, out, accs, s, grid, short_grid, c.seg_small_max,
+  // short segments: one workgroup per compute unit
+  const int short_grid = std::min(cu_count(dev), seg_short_block());
+  return status_of(launch_segmented(x, offsets, nseg, out, accs, chunks, s, grid, short_grid, c.seg_small_max,
                                     c.precombine));
 }
 

@@ -66,6 +66,14 @@ __device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v,
   return ((unsigned long long)hi << 32) | lo;
 }
 
+// A value that every active lane holds (read from LDS, say), made
+// wave-uniform for the compiler, so that loops and branches on it are scalar.
+__device__ __forceinline__ long long uniform_i64(long long v) {
+  const unsigned int lo = (unsigned int)__builtin_amdgcn_readfirstlane((int)(unsigned int)(unsigned long long)v);
+  const unsigned int hi = (unsigned int)__builtin_amdgcn_readfirstlane((int)(unsigned int)((unsigned long long)v >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
 // Sum over the 64 lanes (mod 2^64), returned as a wave-uniform value.
 // Within each row of 16 lanes: swap neighbours, swap pairs, mirror the
 // half-rows, mirror the row (every lane then holds its row sum); the four

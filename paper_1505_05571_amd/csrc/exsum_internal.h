@@ -17,8 +17,10 @@ struct Workspace {
   double *partials = nullptr;          // per-workgroup partials of the inexact sum
   unsigned int *ticket = nullptr;      // ticket of the inexact sum
   int max_grid = 0;                    // capacity of `partials`
-  // segmented calls: one accumulator per workgroup boundary (kMaxGrid)
+  // segmented calls: one accumulator per workgroup boundary (kMaxGrid), then
+  // the short-segment partition's chunk weights (kMaxGrid words)
   GlobalAcc *seg_accs = nullptr;
+  long long *seg_chunks = nullptr;
 };
 
 // Host helpers (api.cpp): EXSUM_* status of a HIP error (clearing the HIP
@@ -55,13 +57,13 @@ int op_block();
 
 // Segmented sums (kernels_seg.hip).
 size_t global_acc_bytes();
-// Two launches: short segments (at most small_max terms) by `short_grid`
-// blocks of wavefronts, long ones by `grid` workgroups.
+// Two launches: long segments (more than small_max terms) by `grid`
+// workgroups, then short ones by `short_grid` workgroups of
+// seg_short_block() threads.  chunks: short_grid words of scratch.
 hipError_t launch_segmented(const double *x, const int64_t *offsets, int64_t nseg, double *out,
-                            GlobalAcc *accs, hipStream_t s, int grid, int short_grid, int64_t small_max,
-                            int precombine);
-int seg_short_waves_per_block();
-
+                            GlobalAcc *accs, long long *chunks, hipStream_t s, int grid, int short_grid,
+                            int64_t small_max, int precombine);
+int seg_short_block();
 
 // One piece of a served request (host and device layout).  `expected` is the
 // request's total number of pieces when this piece belongs to the step that

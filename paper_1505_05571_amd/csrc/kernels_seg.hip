@@ -1,27 +1,29 @@
 // kernels_seg.hip -- many exact sums of uneven length (gfx950): two launches
 // on the caller's stream that write disjoint outputs.
 //
-// Short segments (at most small_max terms, empty ones included) are summed
-// whole by single wavefronts with the small-superaccumulator body and
-// rounded where they are summed (the Performance evaluations find the small
-// method the faster one for short sums).  Wave v of W takes segments
-// [nseg*v/W, nseg*(v+1)/W) and skips the long ones; every wave's work is
-// thus at most ceil(nseg/W) * small_max terms.  The kernel is light (small
-// LDS and register footprint), so many wavefronts share a compute unit and
-// hide each other's memory latency.
+// Long segments (more than small_max terms) are summed first, by workgroups
+// with the large accumulator (carry mode).  Workgroup w of G takes the terms
+// [o0 + N*w/G, o0 + N*(w+1)/G) (N = offsets[nseg] - offsets[0]; G is the
+// grid capped at N, so that no range is empty), so every workgroup reads the
+// same number of bytes of the concatenated input whatever the lengths.  It
+// finds the segment holding its first term with a wavefront-wide search of
+// the offsets and walks the long segments that meet its range in batches of
+// up to 256.  A segment inside one range is rounded by that workgroup; a
+// segment cut by range boundaries adds its pieces into the accumulator slot
+// of the first workgroup that holds one, a ticket counts the pieces (exactly
+// the workgroups wg_of(first) .. wg_of(last)), and the piece that completes
+// the count rounds.  The same launch also sums the weights of the short
+// kernel's chunks of segments, from which that kernel partitions its work.
 //
-// Long segments are summed by workgroups with the large accumulator (carry
-// mode).  Workgroup w of G takes the terms [o0 + N*w/G, o0 + N*(w+1)/G)
-// (N = offsets[nseg] - offsets[0]; G is the grid capped at N, so that no
-// range is empty), so every workgroup reads the same number of bytes of the
-// concatenated input whatever the lengths.  It finds the segment holding its
-// first term with a wavefront-wide search of the offsets and walks the long
-// segments that meet its range in batches of up to 256.  A segment inside
-// one range is rounded by that workgroup; a segment cut by range boundaries
-// adds its pieces into the accumulator slot of the first workgroup that
-// holds one, a ticket counts the pieces (exactly the workgroups
-// wg_of(first) .. wg_of(last)), and the piece that completes the count
-// rounds.
+// Short segments (at most small_max terms, empty ones included) are then
+// summed whole by single wavefronts with the small-superaccumulator body and
+// rounded where they are summed (the Performance evaluations find the small
+// method the faster one for short sums).  One workgroup per compute unit
+// takes an equal share of the total weight (terms plus a fixed cost per
+// segment) and hands its segments to its wavefronts one at a time from an
+// LDS counter, longest first: wavefronts of one compute unit do not progress
+// at the same rate (older ones issue first), so a fixed per-wavefront split
+// leaves a long tail.
 #include "exsum_blocks.h"
 #include "exsum_internal.h"
 
@@ -29,6 +31,10 @@ namespace exsum {
 namespace {
 
 constexpr int kSegBatch = 256;
+// Cost of one short segment beyond its terms (zeroing, rounding, the first
+// load's latency), in terms: the weight the short kernel's partition gives
+// each segment.
+constexpr long long kSegCost = 2048;
 
 // Workgroup of G whose term range contains relative position p (0 <= p < N):
 // the largest w with floor(N*w/G) <= p.
@@ -41,16 +47,38 @@ struct SegShared {
   long long off[kSegBatch + 1];        // a batch of segment offsets
   unsigned int nb;                     // segments of this batch that meet the range
   long long first;                     // first segment of the range
+  long long red[16];                   // wave partial sums
 };
 
 template <int BLOCK, int VEC, int DEPTH>
 __global__ __launch_bounds__(BLOCK) void seg_long_kernel(const double *__restrict__ x,
                                                          const long long *__restrict__ offsets, long long nseg,
                                                          double *__restrict__ out, GlobalAcc *__restrict__ accs,
-                                                         long long small_max, int precombine) {
+                                                         long long small_max, int precombine,
+                                                         long long *__restrict__ chunks, int nchunks) {
   __shared__ SegShared S;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // all lanes active here
+  if (chunks) {
+    // weights of the short kernel's chunks (segments [k*nseg/C, (k+1)*nseg/C))
+    for (long long k = blockIdx.x; k < nchunks; k += gridDim.x) {
+      const long long c0 = k * nseg / nchunks, c1 = (k + 1) * nseg / nchunks;
+      long long t = 0;
+      for (long long i = c0 + tid; i < c1; i += BLOCK) {
+        const long long len = offsets[i + 1] - offsets[i];
+        if (len <= small_max) t += len + kSegCost;
+      }
+      t = wave_sum_i64(t);
+      if (lane == 0) S.red[wave] = t;
+      __syncthreads();
+      if (tid == 0) {
+        long long u = 0;
+        for (int w = 0; w < BLOCK / 64; w++) u += S.red[w];
+        chunks[k] = u;
+      }
+      __syncthreads();
+    }
+  }
   const long long o0 = offsets[0], oN = offsets[nseg];
   const long long N = oN - o0;
   if (N <= 0) return;                                   // no terms: only empty (short) segments
@@ -124,62 +152,211 @@ __global__ __launch_bounds__(BLOCK) void seg_long_kernel(const double *__restric
 }
 
 constexpr int kShortCopies = 8;
+constexpr int kShortBlock = 1024;      // one workgroup per compute unit
+// Length classes: a round's segments are handed out longest class first.
+constexpr long long kClassA = 4096, kClassB = 512;
 
-template <int NW>
+// Inclusive sum over a workgroup (BLOCK threads, every thread calls it).
+// red: BLOCK/64 words of LDS.
+template <int BLOCK>
+__device__ __forceinline__ long long block_incl_scan(long long v, long long *red, long long &total) {
+  constexpr int NW = BLOCK / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const long long u = (long long)__shfl_up((unsigned long long)v, d, 64);
+    if (lane >= d) v += u;
+  }
+  __syncthreads();
+  if (lane == 63) red[wave] = v;
+  __syncthreads();
+  long long before = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < NW; w++) {
+    const long long r = red[w];
+    if (w < wave) before += r;
+    all += r;
+  }
+  total = uniform_i64(all);
+  return v + before;
+}
+
+template <int BLOCK>
 struct ShortShared {
-  long long acc[NW][small_acc_words<kShortCopies>()];
-  unsigned long long spec[NW][4];
+  long long acc[BLOCK / 64][small_acc_words<kShortCopies>()];
+  unsigned long long spec[BLOCK / 64][4];
+  long long lo[BLOCK];                 // a round's segment bounds (also scan scratch)
+  long long hi[BLOCK];
+  int ord[BLOCK];                      // the round's short segments, longest class first
+  int ccount[3][BLOCK / 64];
+  int cnt;                             // 64 x the next entry of ord to hand out
+  long long red[BLOCK / 64];
+  long long first;
 };
 
-// Short segments, one wavefront each.  Offsets are read 64 at a time into
-// the lanes and taken one by one with readlane.
+// Weight of segment i in the partition of the short kernel's work.
+__device__ __forceinline__ long long seg_weight(const long long *__restrict__ offsets, long long i,
+                                                long long small_max) {
+  const long long len = offsets[i + 1] - offsets[i];
+  return len <= small_max ? len + kSegCost : 0;
+}
+
+// First segment of the short kernel's workgroup range that starts at weight
+// position `target`: the smallest i whose exclusive weight prefix is at
+// least target, or nseg.  Chunk k holds segments [k*nseg/C, (k+1)*nseg/C)
+// and chunks[k] their total weight.  Called by every thread.
+template <int BLOCK>
+__device__ long long short_range_start(const long long *__restrict__ offsets, long long nseg, long long small_max,
+                                       const long long *__restrict__ chunks, int C, long long target,
+                                       ShortShared<BLOCK> &S) {
+  const int tid = threadIdx.x;
+  // chunk prefix sums (C <= BLOCK): lo[k] = weight before chunk k
+  long long tot = 0;
+  const long long wk = tid < C ? chunks[tid] : 0;
+  const long long inc = block_incl_scan<BLOCK>(wk, S.red, tot);
+  __syncthreads();
+  S.lo[tid] = inc - wk;
+  if (tid == 0) S.first = 0;
+  __syncthreads();
+  // the last chunk starting at or before target
+  const unsigned long long m = __ballot(tid < C && S.lo[tid] <= target);
+  if ((tid & 63) == 0 && m) atomicMax((unsigned long long *)&S.first, (unsigned long long)(tid + 63 - __clzll(m)));
+  __syncthreads();
+  const long long k = uniform_i64(S.first);
+  long long base = uniform_i64(S.lo[k]);
+  const long long c0 = k * nseg / C, c1 = (k + 1) * nseg / C;
+  __syncthreads();
+  if (tid == 0) S.first = c1;
+  __syncthreads();
+  for (long long r = c0; r < c1; r += BLOCK) {
+    const long long i = r + tid;
+    const long long w = i < c1 ? seg_weight(offsets, i, small_max) : 0;
+    long long step = 0;
+    const long long e = base + block_incl_scan<BLOCK>(w, S.red, step) - w;
+    if (i < c1 && e >= target) atomicMin((unsigned long long *)&S.first, (unsigned long long)i);
+    base += step;
+    __syncthreads();
+    if (uniform_i64(S.first) < c1) break;
+  }
+  const long long f = uniform_i64(S.first);
+  __syncthreads();
+  return f;
+}
+
+// Short segments (at most small_max terms, empty ones included).  Workgroup
+// g of G takes the segments [start(g), start(g+1)): with `plan`, the ranges
+// split the total weight (length + kSegCost over short segments) evenly,
+// found from the chunk weights the long-segment kernel wrote; otherwise they
+// split the segment count.  Within its range a workgroup stages up to BLOCK
+// segments at a time in LDS and its wavefronts take them one by one from an
+// LDS counter, longest class first, each summing a whole segment into its
+// own small accumulator and rounding it.  Handing segments out inside the
+// workgroup keeps every wavefront busy whatever its issue priority.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void seg_short_kernel(const double *__restrict__ x,
                                                           const long long *__restrict__ offsets, long long nseg,
-                                                          double *__restrict__ out, long long small_max) {
+                                                          double *__restrict__ out, long long small_max,
+                                                          const long long *__restrict__ chunks, int plan) {
   constexpr int NW = BLOCK / 64;
-  __shared__ ShortShared<NW> S;
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);   // all lanes active here
+  __shared__ ShortShared<BLOCK> S;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // all lanes active here
+  const long long G = gridDim.x, g = blockIdx.x;
+  long long g0, g1;
+  if (plan) {
+    const int C = (int)G;
+    long long T = 0;
+    {
+      const long long wk = tid < C ? chunks[tid] : 0;
+      (void)block_incl_scan<BLOCK>(wk, S.red, T);
+      __syncthreads();
+    }
+    if (T == 0) return;                                 // no short segments
+    g0 = short_range_start<BLOCK>(offsets, nseg, small_max, chunks, C, (g * T + G - 1) / G, S);
+    g1 = nseg;
+    if (g + 1 < G) g1 = short_range_start<BLOCK>(offsets, nseg, small_max, chunks, C, ((g + 1) * T + G - 1) / G, S);
+  } else {
+    g0 = nseg * g / G;
+    g1 = nseg * (g + 1) / G;
+  }
   long long *acc = S.acc[wave];
   unsigned long long *spec = S.spec[wave];
-  const long long W = (long long)gridDim.x * NW;
-  const long long v = (long long)blockIdx.x * NW + wave;
-  const long long i1 = nseg * (v + 1) / W;
-  for (long long i0 = nseg * v / W; i0 < i1; i0 += 63) {
-    long long idx = i0 + lane;
-    idx = idx < nseg ? idx : nseg;
-    const unsigned long long ov = (unsigned long long)offsets[idx];
-    const int cnt = (int)((i1 - i0 < 63) ? (i1 - i0) : 63);
-    for (int k = 0; k < cnt; k++) {
-      const long long s0 = (long long)readlane_u64(ov, k);
-      const long long s1 = (long long)readlane_u64(ov, k + 1);
-      if (s1 - s0 > small_max) continue;               // long: the other kernel's
-      small_wave_zero<kShortCopies>(acc, spec, lane);
-      small_wave_accumulate<kShortCopies>(acc, spec, SrcF64{x}, s0, s1, lane);
-      wave_merge_and_round(acc, spec, nullptr, 1u, &out[i0 + k], lane);
+  for (long long r0 = g0; r0 < g1; r0 += BLOCK) {
+    const long long i = r0 + tid;
+    long long s0 = 0, s1 = 0;
+    int cls = 3;
+    if (i < g1) {
+      s0 = offsets[i];
+      s1 = offsets[i + 1];
+      const long long len = s1 - s0;
+      if (len <= small_max) cls = len >= kClassA ? 0 : (len >= kClassB ? 1 : 2);
     }
+    S.lo[tid] = s0;
+    S.hi[tid] = s1;
+    const unsigned long long m0 = __ballot(cls == 0), m1 = __ballot(cls == 1), m2 = __ballot(cls == 2);
+    if (lane == 0) {
+      S.ccount[0][wave] = __popcll(m0);
+      S.ccount[1][wave] = __popcll(m1);
+      S.ccount[2][wave] = __popcll(m2);
+    }
+    if (tid == 0) S.cnt = 0;
+    __syncthreads();
+    int total = 0;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      int before = 0, all = 0;
+      for (int w = 0; w < NW; w++) {
+        const int n = S.ccount[c][w];
+        if (w < wave) before += n;
+        all += n;
+      }
+      if (cls == c) {
+        const unsigned long long m = c == 0 ? m0 : (c == 1 ? m1 : m2);
+        S.ord[total + before + __popcll(m & ((1ull << lane) - 1ull))] = tid;
+      }
+      total += all;
+    }
+    total = __builtin_amdgcn_readfirstlane(total);
+    __syncthreads();
+    for (;;) {
+      // every lane adds 1, so one claim advances the counter by 64 and the
+      // first lane's old value (wave-uniform) names the claimed entry; no
+      // value of one lane is broadcast, and the loop stays scalar
+      const int k = __builtin_amdgcn_readfirstlane(atomicAdd(&S.cnt, 1)) >> 6;
+      if (k >= total) break;
+      const int j = __builtin_amdgcn_readfirstlane(S.ord[k]);
+      const long long a = uniform_i64(S.lo[j]), b = uniform_i64(S.hi[j]);
+      small_wave_zero<kShortCopies>(acc, spec, lane);
+      small_wave_accumulate<kShortCopies>(acc, spec, SrcF64{x}, a, b, lane);
+      wave_merge_and_round(acc, spec, nullptr, 1u, &out[r0 + j], lane);
+    }
+    __syncthreads();
   }
 }
-
-constexpr int kShortBlock = 256;
 
 }  // namespace
 
 hipError_t launch_segmented(const double *x, const int64_t *offsets, int64_t nseg, double *out, GlobalAcc *accs,
-                            hipStream_t s, int grid, int short_grid, int64_t small_max, int precombine) {
+                            long long *chunks, hipStream_t s, int grid, int short_grid, int64_t small_max,
+                            int precombine) {
   if (grid < 1) grid = 1;
   if (short_grid < 1) short_grid = 1;
-  hipLaunchKernelGGL((seg_short_kernel<kShortBlock>), dim3(short_grid), dim3(kShortBlock), 0, s, x,
-                     (const long long *)offsets, (long long)nseg, out, (long long)small_max);
+  if (short_grid > kShortBlock) short_grid = kShortBlock;
+  // the weight partition needs at most BLOCK segments per chunk
+  const int plan = nseg <= (int64_t)short_grid * kShortBlock ? 1 : 0;
+  hipLaunchKernelGGL((seg_long_kernel<512, 4, 2>), dim3(grid), dim3(512), 0, s, x, (const long long *)offsets,
+                     (long long)nseg, out, accs, (long long)small_max, precombine, plan ? chunks : nullptr,
+                     short_grid);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((seg_long_kernel<512, 4, 2>), dim3(grid), dim3(512), 0, s, x, (const long long *)offsets,
-                     (long long)nseg, out, accs, (long long)small_max, precombine);
+  hipLaunchKernelGGL((seg_short_kernel<kShortBlock>), dim3(short_grid), dim3(kShortBlock), 0, s, x,
+                     (const long long *)offsets, (long long)nseg, out, (long long)small_max,
+                     (const long long *)chunks, plan);
   return hipGetLastError();
 }
 
-int seg_short_waves_per_block() { return kShortBlock / 64; }
+int seg_short_block() { return kShortBlock; }
 
 size_t global_acc_bytes() { return sizeof(GlobalAcc); }
 
