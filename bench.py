@@ -50,6 +50,8 @@ WORKLOADS = {
     "adversarial": "adversarial n=2^27 (1.07 GB binary64; hot chunk half, cancelling pairs, tiny terms, 1% near DBL_MAX)",
     "small_normal": "small_normal n=1000 (sign uniform, |N(0,1)| 2^k, k in [-20,20]); latency",
     "segments": "segments nseg=65536 lognormal(median 1000, sigma 2) clipped [1,1e6]; one batched call",
+    "segments_b": "segments nseg=65536 lognormal(median 1000, sigma 1.63) clipped [1,1e6] (about 2.5e8 terms); "
+                  "one batched call",
     "copy": "device-to-device copy of 800 MB (reference for HBM bandwidth and counter calibration)",
     "dot": "dot product of two 5e7-term vectors (uniform_exponent draws, exponents [-250, 250]; 800 MB read)",
     "sqnorm": "squared norm of 1e8 terms (uniform_exponent draws, exponents [-250, 250]; 800 MB)",
@@ -91,6 +93,8 @@ def make_input(name: str):
         return W.small_normal(1000, seed=0), None
     if name == "segments":
         return W.segments(nseg=65536, seed=0)
+    if name == "segments_b":
+        return W.segments(nseg=65536, seed=0, sigma=1.63)
     if name == "copy":
         return W.uniform_exponent(10 ** 8, seed=0), None
     raise ValueError(name)
@@ -420,6 +424,29 @@ def main():
         return s.elapsed_time(e) / 1e3 / reps
 
     inexact = None
+    segmented = None
+    if off_t is not None:
+        nseg = int(offsets.size - 1)
+        # the same call captured once in a HIP graph and replayed
+        gs = torch.cuda.Stream()
+        gout = torch.empty_like(out)
+        with torch.cuda.stream(gs):
+            ex.exsum_segmented_f64(bufs[0], off_t, out=gout, stream=gs)   # allocates gs's workspace
+        gs.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=gs):
+            ex.exsum_segmented_f64(bufs[0], off_t, out=gout, stream=gs)
+        t_graph = time_fn(lambda i: graph.replay(), 20)
+        graph_ok = bool(np.array_equal(gout.cpu().numpy().view(np.uint64)[:nseg], want))
+        segmented = {"segments": nseg, "segments_per_s": round(nseg / avg_kernel_s, 1),
+                     "graph_replay_ms": round(t_graph * 1e3, 4), "graph_replay_parity": graph_ok}
+        try:
+            lens_t = torch.from_numpy(np.diff(offsets)).to(dev)
+            t_seg = time_fn(lambda i: torch.segment_reduce(bufs[i & 1], "sum", lengths=lens_t), 10)
+            inexact = {"torch_segment_reduce_GBs": round(bytes_per_step / t_seg / 1e9, 1),
+                       "exact_over_inexact_time": round(avg_kernel_s / t_seg, 3)}
+        except RuntimeError as e:
+            inexact = {"torch_segment_reduce": "unavailable: %s" % str(e).splitlines()[0][:120]}
     if off_t is None:
         t_hip = time_fn(lambda i: ex.exsum_inexact_f64(bufs[i & 1], out=out, stream=stream), 20)
         t_torch = time_fn(lambda i: torch.sum(bufs[i & 1]), 20)
@@ -453,6 +480,8 @@ def main():
         "inexact": inexact,
         "parity": parity,
     }
+    if segmented is not None:
+        result["segmented"] = segmented
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(x, offsets)
     print(json.dumps(result), flush=True)

@@ -795,17 +795,35 @@ template <class Src>
 __device__ __forceinline__ void small_batch_add(long long *mine, unsigned long long *spec, const Src &src,
                                                 const typename Src::Raw (&b)[kSmallU], long long base, long long hi,
                                                 int lane) {
+  unsigned long long t[kSmallU];
+  bool special = false;
+#pragma unroll
+  for (int j = 0; j < kSmallU; j++) {
+    t[j] = src.sterm(b[j]);
+    special |= is_special(t[j]);
+  }
+  if (base + 64 * kSmallU <= hi && !__any(special)) {
+    // a whole batch of finite terms (the common case): no per-term branch
+#pragma unroll
+    for (int j = 0; j < kSmallU; j++) {
+      int h;
+      long long plo, phi;
+      term_pieces(t[j], h, plo, phi);
+      atomicAdd((unsigned long long *)&mine[h], (unsigned long long)plo);
+      atomicAdd((unsigned long long *)&mine[h + 1], (unsigned long long)phi);
+    }
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < kSmallU; j++) {
     const long long i = base + (long long)j * 64 + lane;
     if (i < hi) {
-      const unsigned long long t = src.sterm(b[j]);
-      if (is_special(t)) {
-        note_special(t, &spec[0], &spec[1], &spec[2]);
+      if (is_special(t[j])) {
+        note_special(t[j], &spec[0], &spec[1], &spec[2]);
       } else {
         int h;
         long long plo, phi;
-        term_pieces(t, h, plo, phi);
+        term_pieces(t[j], h, plo, phi);
         atomicAdd((unsigned long long *)&mine[h], (unsigned long long)plo);
         atomicAdd((unsigned long long *)&mine[h + 1], (unsigned long long)phi);
       }

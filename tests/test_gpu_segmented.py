@@ -143,3 +143,27 @@ def test_full_size_batched_workload(ex):
     want = oracle.segmented_f64(x, off)
     got = seg_bits(ex, dev(x), dev(off))
     assert np.array_equal(got, want)
+
+
+def test_full_size_batched_workload_sigma_163(ex):
+    # the same batch with sigma 1.63 (about 2.5e8 terms), at several
+    # short/long thresholds: every threshold gives the same bits
+    x, off = W.segments(nseg=65536, seed=0, sigma=1.63)
+    want = oracle.segmented_f64(x, off)
+    xt, offt = dev(x), dev(off)
+    assert np.array_equal(seg_bits(ex, xt, offt), want)
+    for sm in (0, 4096, 65536, 1 << 20):
+        assert np.array_equal(seg_bits(ex, xt, offt, seg_small_max=sm), want), sm
+
+
+def test_many_segments_count_partition(ex):
+    # more segments than the weight partition takes (workgroups x 1024): the
+    # short kernel splits them by count instead; same bits either way
+    x, off = W.segments(nseg=300000, seed=8, median=20.0, sigma=1.5, hi=20000)
+    want = oracle.segmented_f64(x, off)
+    xt, offt = dev(x), dev(off)
+    assert np.array_equal(seg_bits(ex, xt, offt), want)
+    assert np.array_equal(seg_bits(ex, xt, offt, seg_small_max=64), want)
+    # a slice below the threshold takes the weight partition
+    sub = off[:200001] - off[0]
+    assert np.array_equal(seg_bits(ex, dev(x[:int(sub[-1])]), dev(sub)), want[:200000])
