@@ -62,6 +62,14 @@ WORKLOADS = {
 }
 
 
+# launch configuration the run used: the library defaults, or the tuner's pick
+TUNING = {"label": "defaults", "config": None}
+
+
+def tuning_info():
+    return TUNING["label"] if TUNING["config"] is None else {"label": TUNING["label"], "config": TUNING["config"]}
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
@@ -214,7 +222,7 @@ def serve_bench(args):
         "value": head["GBs"], "unit": "GB/s", "n_gpus": 1, "steps": nreq, "warmup": 20,
         "ms_per_step": round(head["makespan_s"] * 1e3 / nreq, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int64", "data": "synthetic",
-        "config": {"workload": WORKLOADS["serve"], "requests": nreq, "terms": int(lens.sum()),
+        "config": {"workload": WORKLOADS["serve"], "tuning": tuning_info(), "requests": nreq, "terms": int(lens.sum()),
                    "mean_serial_service_ms": round(mean_service * 1e3, 4)},
         "loads": loads,
         "parity": {"batched_and_serial_equal": served_ok, "oracle_sample_requests": int(pick.size),
@@ -298,7 +306,7 @@ def op_bench(args):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int64", "data": "synthetic",
-        "config": {"workload": WORKLOADS[w], "n_terms": n, "input_dtype": "f32" if w == "f32" else "f64",
+        "config": {"workload": WORKLOADS[w], "tuning": tuning_info(), "n_terms": n, "input_dtype": "f32" if w == "f32" else "f64",
                    "seed": 0, "terms_per_s": round(n * args.steps / wall, 1)},
         "roofline": {"bound": "hbm", "achieved": round(bytes_per_step / avg / 1e9, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(bytes_per_step / avg / 1e9 / HBM_PEAK_GBS, 4), "traffic": None},
@@ -326,13 +334,19 @@ def main():
     ap.add_argument("--workload", default="uniform_exponent", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=20000)
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the library's configuration tuner before the workload (untimed)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build measures one GPU only; --gpus %d (WORLD_SIZE=%d) is not supported. "
-              "How the exact sum would shard across GPUs is described in DESIGN.md." % (args.gpus, world),
-              file=sys.stderr)
+        print("bench.py measures a single GPU: --gpus %d (WORLD_SIZE=%d) is not supported."
+              % (args.gpus, world), file=sys.stderr)
         sys.exit(2)
+    if args.autotune:
+        import paper_1505_05571_amd as ex
+        ex.load_library()
+        TUNING["label"] = "autotuned"
+        TUNING["config"] = ex.exsum_autotune()["config"]
 
     if args.workload == "serve":
         return serve_bench(args)
@@ -468,7 +482,7 @@ def main():
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload], "n_terms": n, "input_dtype": "f64", "seed": 0,
+        "config": {"workload": WORKLOADS[args.workload], "tuning": tuning_info(), "n_terms": n, "input_dtype": "f64", "seed": 0,
                    "terms_per_s": round(n * args.steps / wall, 1)},
         "latency_ms": {"calls": ncalls,
                        "device_p50": round(float(np.percentile(ev_ms, 50)), 4),

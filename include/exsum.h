@@ -24,9 +24,9 @@
  * beyond 8 bytes, and every call is asynchronous on `stream` (a hipStream_t
  * passed as void*; NULL is the null stream): results are valid once the
  * stream reaches the call.  The library keeps a small per-(device, stream)
- * workspace (merge rows, accumulators and tickets, about 10 MiB) that it
- * allocates on the first call
- * on that stream, zero-initialises synchronously, and keeps clean itself
+ * workspace (merge accumulators, tickets and segment slots, about 5 MiB)
+ * that it allocates on the first call on that stream, zero-initialises
+ * synchronously, and keeps clean itself
  * (each call leaves it zeroed); exsum_release() frees it.  Calls on the same
  * stream are ordered; calls on different streams use different workspaces
  * and may overlap.
@@ -154,6 +154,37 @@ typedef struct {
     int32_t seg_grid;
     int64_t seg_small_max;
 } exsum_config;
+
+/*
+ * exsum_autotune -- pick the launch configuration for the current device by
+ * timing candidates on synthetic inputs (10^8 terms of three exponent
+ * distributions for the large-kernel variant, scored by the worst ratio to
+ * the fastest candidate; lengths 512 .. 65536 for the small/large crossover;
+ * a batch of 16384 lognormal segments for seg_small_max), and make the
+ * chosen configuration the process configuration.  Every candidate's result
+ * bits are compared with the others'; a difference (a defect: configurations
+ * change only speed) returns EXSUM_EDEVICE.  Takes a few seconds and 1.6 GB
+ * of device memory,
+ * allocated and freed inside the call; synchronises `stream`.  On any error
+ * the previous configuration stays in force.
+ *   cache_path : if not NULL, the result is also written there as JSON
+ *                (device name, architecture, compute units, configuration,
+ *                the measured times), for exsum_load_tuning().
+ *   report     : if report_len > 0, the same JSON, truncated to
+ *                report_len - 1 bytes and NUL-terminated (host memory).
+ * Changes the configuration used by concurrent calls on other threads (the
+ * bits they compute are unaffected).
+ */
+int exsum_autotune(const char *cache_path, char *report, int64_t report_len, void *stream);
+
+/*
+ * exsum_load_tuning -- make the configuration stored by exsum_autotune() in
+ * cache_path the process configuration.  EXSUM_EINVAL if the file is
+ * missing or malformed, holds an out-of-range configuration, or was written
+ * on a device with another name, architecture or compute-unit count than
+ * the current one.
+ */
+int exsum_load_tuning(const char *cache_path);
 
 /* Current configuration of the calling process (defaults until set). */
 int exsum_get_config(exsum_config *cfg);

@@ -15,6 +15,7 @@ __all__ = [
     "ExsumError", "ExsumConfig", "library_path", "load_library",
     "exsum_f64", "exsum_segmented_f64", "exsum_inexact_f64", "exsum_f64_cfg",
     "exsum_get_config", "exsum_set_config", "exsum_release", "exsum_status_string",
+    "exsum_autotune", "exsum_load_tuning",
     "ServerConfig", "Server", "exsum_server_default_config", "exsum_server_plan", "exsum_serial_replay",
     "exsum_sqnorm_f64", "exsum_dot_f64", "exsum_mean_f64", "exsum_f32", "Accumulator", "EXSUM_ACC_BYTES",
     "EXPORTED_SYMBOLS",
@@ -36,6 +37,7 @@ EXPORTED_SYMBOLS = [
     "exsum_server_replay", "exsum_serial_replay", "exsum_server_plan",
     "exsum_sqnorm_f64", "exsum_dot_f64", "exsum_mean_f64", "exsum_f32",
     "exsum_acc_zero", "exsum_acc_add_f64", "exsum_acc_merge", "exsum_acc_round_f64",
+    "exsum_autotune", "exsum_load_tuning",
 ]
 
 EXSUM_ACC_BYTES = 576
@@ -93,6 +95,13 @@ def load_library():
         if not os.path.exists(_LIB_PATH):
             raise RuntimeError("libexsum.so is not built (run __graft_entry__.build() or "
                                "python -m paper_1505_05571_amd.build); there is no fallback")
+        # PyTorch first, so that the library and PyTorch share one HIP runtime
+        # (PyTorch's): loaded the other way round, the library's first device
+        # query can find no device
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(_LIB_PATH)
         P, I64, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
         lib.exsum_status_string.argtypes = [I32]
@@ -132,6 +141,10 @@ def load_library():
         lib.exsum_acc_add_f64.argtypes = [P, P, I64, P]
         lib.exsum_acc_merge.argtypes = [P, P, P]
         lib.exsum_acc_round_f64.argtypes = [P, P, P]
+        lib.exsum_autotune.argtypes = [ctypes.c_char_p, ctypes.c_char_p, I64, P]
+        lib.exsum_autotune.restype = I32
+        lib.exsum_load_tuning.argtypes = [ctypes.c_char_p]
+        lib.exsum_load_tuning.restype = I32
         for name in ("exsum_sqnorm_f64", "exsum_dot_f64", "exsum_mean_f64", "exsum_f32", "exsum_acc_zero",
                      "exsum_acc_add_f64", "exsum_acc_merge", "exsum_acc_round_f64"):
             getattr(lib, name).restype = I32
@@ -330,6 +343,26 @@ def exsum_get_config() -> ExsumConfig:
 
 def exsum_set_config(cfg: ExsumConfig) -> None:
     _check(load_library().exsum_set_config(ctypes.byref(cfg)), "exsum_set_config")
+
+
+def exsum_autotune(cache_path: str | None = None, stream=None) -> dict:
+    """Time candidate launch configurations on the current device, make the
+    fastest the process configuration and return the tuner's JSON report
+    (also written to cache_path if given)."""
+    import json
+    buf = ctypes.create_string_buffer(1 << 16)
+    path = cache_path.encode() if cache_path else None
+    st = load_library().exsum_autotune(path, buf, len(buf), _stream_handle(stream))
+    if st != EXSUM_OK:
+        detail = json.loads(buf.value.decode() or "{}").get("error", "")
+        raise ExsumError(st, "exsum_autotune (%s)" % detail)
+    return json.loads(buf.value.decode())
+
+
+def exsum_load_tuning(cache_path: str) -> None:
+    """Make the configuration stored by exsum_autotune() the process
+    configuration (same kind of device only)."""
+    _check(load_library().exsum_load_tuning(cache_path.encode()), "exsum_load_tuning")
 
 
 def exsum_release() -> None:

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libexsum.so")
-SOURCES = ["kernels_sum.hip", "kernels_seg.hip", "kernels_serve.hip", "serve.cpp", "api.cpp"]
+SOURCES = ["kernels_sum.hip", "kernels_seg.hip", "kernels_serve.hip", "tune.hip", "serve.cpp", "api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -212,3 +212,16 @@ def test_further_reductions_host_checks(lib):
     assert lib.exsum_acc_merge(P(64), P(96), None) == 1
     assert lib.exsum_acc_round_f64(P(64), None, None) == 1
     assert ex.EXSUM_ACC_BYTES == 576
+
+
+def test_tuning_file_checks(lib, tmp_path):
+    # checked on the host before any device query
+    assert lib.exsum_load_tuning(None) == 1
+    assert lib.exsum_load_tuning(str(tmp_path / "missing.json").encode()) == 1
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"exsum_tuning": 1, "device": "x"}')
+    assert lib.exsum_load_tuning(str(bad).encode()) == 1
+    other = tmp_path / "v2.json"
+    other.write_text('{"exsum_tuning": 2, "device": "x", "arch": "y", "cus": 1, "config": {}}')
+    assert lib.exsum_load_tuning(str(other).encode()) == 1
+    assert lib.exsum_autotune(None, None, -1, None) == 1
