@@ -135,7 +135,7 @@ int exsum_inexact_f64(const double *x, int64_t n, double *out, void *stream);
  *   small_max   : inputs with n <= small_max use the small-only kernel.
  *   small_grid  : workgroups of the small-only kernel; 0 = automatic.
  *   seg_grid    : workgroups of the segmented call's long-segment kernel;
- *                 0 = one per compute unit.
+ *                 0 = two per compute unit.
  *   seg_small_max : segments of at most this many terms (0 .. 2^20) are
  *                   summed by one wavefront with the small accumulator
  *                   alone; longer ones by workgroups with the large one.

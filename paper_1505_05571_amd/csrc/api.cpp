@@ -220,7 +220,7 @@ int exsum_segmented_f64(const double *x, const int64_t *offsets, int64_t nseg, d
   int st = get_workspace(s, &w, &dev);
   if (st != EXSUM_OK) return st;
   int grid = c.seg_grid;
-  if (grid == 0) grid = cu_count(dev);
+  if (grid == 0) grid = 2 * cu_count(dev);           // two long-segment workgroups per compute unit
   GlobalAcc *accs = nullptr;
   long long *chunks = nullptr;
   {
