@@ -436,10 +436,21 @@ struct SrcF32 {
   __device__ static Vec load_plain(Ptr p, long long k) { return p[k]; }
   __device__ static Vec zero() { return make_uint4(0u, 0u, 0u, 0u); }
   __device__ void terms(const Vec &v, unsigned long long (&t)[4]) const {
-    t[0] = f32_to_f64_bits(v.x);
-    t[1] = f32_to_f64_bits(v.y);
-    t[2] = f32_to_f64_bits(v.z);
-    t[3] = f32_to_f64_bits(v.w);
+    const unsigned int w[4] = {v.x, v.y, v.z, v.w};
+    bool normal = true;
+#pragma unroll
+    for (int k = 0; k < 4; k++) normal &= (((w[k] >> 23) & 255u) - 1u) < 254u;
+    if (__all(normal)) {
+      // every term of the wave's vector is a normal number (the common case):
+      // the exponent is rebiased by an add and the fraction moves up 29 bits
+#pragma unroll
+      for (int k = 0; k < 4; k++)
+        t[k] = ((unsigned long long)(w[k] & 0x80000000u) << 32) |
+               ((((unsigned long long)(w[k] & 0x7FFFFFFFu)) << 29) + (896ull << 52));
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; k++) t[k] = f32_to_f64_bits(w[k]);
+    }
   }
   __device__ Raw sload(long long i) const { return __float_as_uint(x[i]); }
   __device__ unsigned long long sterm(Raw r) const { return f32_to_f64_bits(r); }
