@@ -61,6 +61,8 @@ def _load():
         lib.exo_sqnorm_f64.restype = ctypes.c_uint64
         lib.exo_sum_f32.argtypes = [P, I64]
         lib.exo_sum_f32.restype = ctypes.c_uint32
+        lib.exo_dot_f32.argtypes = [P, P, I64]
+        lib.exo_dot_f32.restype = ctypes.c_uint32
         lib.exo_sum_f64_mt.argtypes = [P, I64, ctypes.c_int]
         lib.exo_sum_f64_mt.restype = ctypes.c_uint64
         _lib = lib
@@ -134,6 +136,15 @@ def sum_f32(x) -> np.uint32:
     """Bits of the correctly rounded (binary32) exact sum of binary32 values."""
     a = np.ascontiguousarray(x, dtype=np.float32)
     return np.uint32(_load().exo_sum_f32(_ptr(a), a.size))
+
+
+def dot_f32(x, y) -> np.uint32:
+    """Bits of the exact dot product of two binary32 vectors, rounded once to
+    binary32 (the products are exact in binary64)."""
+    a = np.ascontiguousarray(x, dtype=np.float32)
+    b = np.ascontiguousarray(y, dtype=np.float32)
+    assert a.size == b.size
+    return np.uint32(_load().exo_dot_f32(_ptr(a), _ptr(b), a.size))
 
 
 def bits_to_f64(b) -> float:

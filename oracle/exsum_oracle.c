@@ -161,6 +161,16 @@ static int wide_any_below(const wide_t *a, int pos)
     return 0;
 }
 
+/* r = a >> s (s >= 1), with every discarded bit ORed into bit 0 of r. */
+static void wide_shr_sticky(wide_t *r, const wide_t *a, int s)
+{
+    for (int i = 0; i < LIMBS; i++) {
+        int pos = i * 64 + s;
+        r->w[i] = pos < LIMBS * 64 ? wide_bits_at(a, pos) : 0;
+    }
+    if (wide_any_below(a, s)) r->w[0] |= 1;
+}
+
 /* q = a / d, returns a % d.  d > 0. */
 static uint64_t wide_divmod_u64(wide_t *q, const wide_t *a, uint64_t d)
 {
@@ -367,6 +377,43 @@ uint32_t exo_sum_f32(const float *x, int64_t n)
     acc_init(&acc);
     for (int64_t i = 0; i < n; i++) acc_add_f32(&acc, x[i]);
     return (uint32_t)acc_result(&acc, 1, 23, 255, 32);
+}
+
+/*
+ * Exact dot product of binary32 vectors (Introduction: the single-precision
+ * variant; Performance evaluations: the dot product).  Each product of two
+ * binary32 values is exact as a binary64 value (24-bit by 24-bit mantissas
+ * fit in 53 bits, and the exponents stay inside the binary64 range), so the
+ * products are formed in binary64, summed exactly, and the sum is rounded
+ * once to binary32.  The accumulator counts units of 2^-1074; binary32's
+ * smallest unit is 2^-149, 2^925 of them.  Two more bits are kept (units of
+ * 2^-151) with everything below folded into a sticky bit, and the quotient
+ * by 4 is rounded in binary32.  A nonzero sum that rounds to zero gives +0,
+ * as for the mean.  A NaN product maps back to binary32 by dropping the 29
+ * low payload bits.
+ */
+uint32_t exo_dot_f32(const float *x, const float *y, int64_t n)
+{
+    acc_t acc;
+    acc_init(&acc);
+    for (int64_t i = 0; i < n; i++) {
+        volatile double p = (double)x[i] * (double)y[i];   /* exact */
+        acc_add_f64(&acc, p);
+    }
+    if (acc.nan_bits) return 0x7FC00000u | (uint32_t)((acc.nan_bits >> 29) & 0x7FFFFFu);
+    if (acc.pos_inf && acc.neg_inf) return 0x7FC00000u;
+    if (acc.pos_inf) return 0x7F800000u;
+    if (acc.neg_inf) return 0xFF800000u;
+    int c = wide_cmp(&acc.pos, &acc.neg);
+    if (c == 0) return 0;
+    wide_t A, B;
+    uint32_t s;
+    if (c > 0) { wide_sub(&A, &acc.pos, &acc.neg); s = 0; }
+    else       { wide_sub(&A, &acc.neg, &acc.pos); s = 0x80000000u; }
+    wide_shr_sticky(&B, &A, 923);
+    uint64_t mag = round_quotient(&B, 4, 23, 255);
+    if (mag == 0) return 0;
+    return s | (uint32_t)mag;
 }
 
 /* Multi-threaded variant, for timing the CPU baseline only: contiguous

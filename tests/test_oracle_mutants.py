@@ -108,3 +108,79 @@ def test_mutant_is_caught(tmp_path, name):
     assert old in text, "mutation site not found: " + name
     mutated = text.replace(old, new, 1)
     assert pins_pass(build_variant(tmp_path, name, mutated)) is False
+
+
+# ---- the binary32 dot product ------------------------------------------------
+
+DOT32_MUTANTS = {
+    "dot32_shift_off_by_one": ("wide_shr_sticky(&B, &A, 923);", "wide_shr_sticky(&B, &A, 924);"),
+    "dot32_sticky_dropped": ("if (wide_any_below(a, s)) r->w[0] |= 1;", ""),
+    "dot32_divisor": ("uint64_t mag = round_quotient(&B, 4, 23, 255);", "uint64_t mag = round_quotient(&B, 2, 23, 255);"),
+    "dot32_negative_zero": ("    if (mag == 0) return 0;\n    return s | (uint32_t)mag;",
+                            "    return s | (uint32_t)mag;"),
+    "dot32_nan_payload": ("((acc.nan_bits >> 29) & 0x7FFFFFu)", "((acc.nan_bits >> 28) & 0x7FFFFFu)"),
+}
+
+
+def f32_round_bits(fr: Fraction) -> int:
+    if fr == 0:
+        return 0
+    s = 0x80000000 if fr < 0 else 0
+    a = abs(fr)
+    e = a.numerator.bit_length() - a.denominator.bit_length()
+    if Fraction(2) ** e > a:
+        e -= 1
+    if Fraction(2) ** (e + 1) <= a:
+        e += 1
+    ulp = Fraction(2) ** (max(e, -126) - 23)
+    q = a / ulp
+    k = q.numerator // q.denominator
+    rem = q - k
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and k % 2 == 1):
+        k += 1
+    if k == 0:
+        return 0
+    val = k * ulp
+    if val >= Fraction(2) ** 128:
+        return s | 0x7F800000
+    return s | int(np.array([np.float32(float(val))]).view(np.uint32)[0])
+
+
+def dot32_pins_pass(lib) -> bool:
+    lib.exo_dot_f32.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
+    lib.exo_dot_f32.restype = ctypes.c_uint32
+
+    def d(x, y):
+        a = np.ascontiguousarray(x, dtype=np.float32)
+        b = np.ascontiguousarray(y, dtype=np.float32)
+        return int(lib.exo_dot_f32(ctypes.c_void_p(a.ctypes.data), ctypes.c_void_p(b.ctypes.data), a.size))
+
+    rng = np.random.default_rng(43)
+    checks = []
+    for _ in range(300):
+        n = int(rng.integers(1, 8))
+        x = (rng.standard_normal(n) * np.exp2(rng.integers(-90, 90, size=n))).astype(np.float32)
+        y = (rng.standard_normal(n) * np.exp2(rng.integers(-90, 90, size=n))).astype(np.float32)
+        exact = sum((Fraction(float(a)) * Fraction(float(b)) for a, b in zip(x, y)), Fraction(0))
+        checks.append(d(x, y) == f32_round_bits(exact))
+    t = np.float32(2.0 ** -75)
+    checks.append(d([t] * 3, [t] * 3) == 2)
+    checks.append(d([-3.0, 3.0, -t], [5.0, 5.0, t]) == 0)
+    u = np.float32(2.0 ** -100)
+    checks.append(d([t, u], [t, u]) == 1)                                  # just above half a unit
+    checks.append(d([1.0, 2.0 ** -12, u], [1.0, 2.0 ** -12, u]) == 0x3F800001)   # just above a tie
+    q = np.array([0x7FC01234], dtype=np.uint32).view(np.float32)[0]
+    checks.append(d([q], [2.0]) == 0x7FC01234)
+    return all(checks)
+
+
+def test_unmodified_oracle_passes_dot32(tmp_path):
+    assert dot32_pins_pass(build_variant(tmp_path, "orig32", open(SRC).read()))
+
+
+@pytest.mark.parametrize("name", sorted(DOT32_MUTANTS))
+def test_dot32_mutant_is_caught(tmp_path, name):
+    old, new = DOT32_MUTANTS[name]
+    text = open(SRC).read()
+    assert old in text, "mutation site not found: " + name
+    assert dot32_pins_pass(build_variant(tmp_path, name, text.replace(old, new, 1))) is False

@@ -361,3 +361,103 @@ def test_f32_exact_in_double_sums():
         got = int(oracle.sum_f32(x))
         assert got == (0 if exp == 0 else int(np.array([exp]).view(np.uint32)[0]))
     assert checked > 300
+
+
+# ---- binary32 dot product --------------------------------------------------
+
+def f32_round_bits(fr: Fraction) -> int:
+    """Bits of a rational rounded to binary32, ties to even, written out from
+    the format's definition (a result of magnitude zero is +0)."""
+    if fr == 0:
+        return 0
+    s = 0x80000000 if fr < 0 else 0
+    a = abs(fr)
+    e = a.numerator.bit_length() - a.denominator.bit_length()
+    if Fraction(2) ** e > a:
+        e -= 1
+    if Fraction(2) ** (e + 1) <= a:
+        e += 1
+    ulp = Fraction(2) ** (max(e, -126) - 23)
+    q = a / ulp
+    k = q.numerator // q.denominator
+    rem = q - k
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and k % 2 == 1):
+        k += 1
+    if k == 0:
+        return 0
+    val = k * ulp
+    if val >= Fraction(2) ** 128:
+        return s | 0x7F800000
+    return s | int(np.array([np.float32(float(val))]).view(np.uint32)[0])
+
+
+def f32_words(rng, n):
+    """Random binary32 values over the whole finite range, denormals included."""
+    b = rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+    e = (b >> np.uint32(23)) & np.uint32(255)
+    b = np.where(e == 255, b ^ np.uint32(1 << 23), b)
+    return b.view(np.float32)
+
+
+def test_f32_round_helper_matches_hardware_casts():
+    # the test's own rounding, checked against numpy's binary64 -> binary32
+    # cast on values that are exact in binary64 (one rounding only)
+    rng = np.random.default_rng(40)
+    d = np.ldexp(rng.standard_normal(5000), rng.integers(-160, 130, size=5000))
+    with np.errstate(over="ignore"):
+        for v in d:
+            hw = np.float32(v)
+            want = 0 if hw == 0 else int(np.array([hw]).view(np.uint32)[0])
+            if math.isinf(hw):
+                want = int(np.array([hw]).view(np.uint32)[0])
+            assert f32_round_bits(Fraction(float(v))) == want, v
+
+
+def test_dot_f32_bruteforce():
+    rng = np.random.default_rng(41)
+    for _ in range(600):
+        n = int(rng.integers(1, 12))
+        if rng.random() < 0.5:
+            x, y = f32_words(rng, n), f32_words(rng, n)
+        else:
+            x = (rng.standard_normal(n) * np.exp2(rng.integers(-80, 80, size=n))).astype(np.float32)
+            y = (rng.standard_normal(n) * np.exp2(rng.integers(-80, 80, size=n))).astype(np.float32)
+        exact = sum((Fraction(float(a)) * Fraction(float(b)) for a, b in zip(x, y)), Fraction(0))
+        assert int(oracle.dot_f32(x, y)) == f32_round_bits(exact), (x, y)
+
+
+def test_dot_f32_single_products_and_cancellation():
+    rng = np.random.default_rng(42)
+    x, y = f32_words(rng, 3000), f32_words(rng, 3000)
+    with np.errstate(over="ignore", under="ignore"):
+        for a, b in zip(x, y):
+            p = np.float32(np.float64(a) * np.float64(b))      # the exact product, rounded once
+            want = int(np.array([p]).view(np.uint32)[0])
+            if p == 0:
+                want = 0
+            assert int(oracle.dot_f32([a], [b])) == want, (a, b)
+    # products that cancel exactly leave the small ones; all below binary32's
+    # smallest denormal: the sum rounds to +0 or to the smallest denormal
+    tiny = np.float32(2.0 ** -100)
+    assert int(oracle.dot_f32([3.0, -3.0, tiny], [5.0, 5.0, tiny])) == 0          # 2^-200 -> +0
+    assert int(oracle.dot_f32([tiny, -tiny], [tiny, tiny])) == 0                  # exact zero
+    d = np.float32(2.0 ** -75)
+    assert int(oracle.dot_f32([d] * 3, [d] * 3)) == 2                            # 3 * 2^-150 -> 2 units
+    assert int(oracle.dot_f32([d], [d])) == 0                                    # half a unit, ties to even
+    u = np.float32(2.0 ** -100)
+    assert int(oracle.dot_f32([d, u], [d, u])) == 1                              # just above half a unit
+    assert int(oracle.dot_f32([1.0, 2.0 ** -12, u], [1.0, 2.0 ** -12, u])) == 0x3F800001   # just above a tie
+    assert int(oracle.dot_f32([1.0, 2.0 ** -12], [1.0, 2.0 ** -12])) == 0x3F800000         # the tie itself
+
+
+def test_dot_f32_specials():
+    inf, nan = np.float32(np.inf), np.float32(np.nan)
+    assert int(oracle.dot_f32([inf, 1.0], [1.0, 2.0])) == 0x7F800000
+    assert int(oracle.dot_f32([inf], [-1.0])) == 0xFF800000
+    assert int(oracle.dot_f32([inf, inf], [1.0, -1.0])) == 0x7FC00000
+    assert int(oracle.dot_f32([inf], [0.0])) == 0x7FC00000                   # inf * 0 is the default NaN
+    q = np.array([0x7FC01234], dtype=np.uint32).view(np.float32)[0]
+    assert int(oracle.dot_f32([q, 1.0], [2.0, 3.0])) == 0x7FC01234            # payload kept
+    fmax = np.finfo(np.float32).max
+    assert int(oracle.dot_f32([fmax, fmax], [2.0, -1.0])) == int(np.array([fmax]).view(np.uint32)[0])
+    assert int(oracle.dot_f32([fmax], [2.0])) == 0x7F800000
