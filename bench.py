@@ -57,6 +57,7 @@ WORKLOADS = {
     "sqnorm": "squared norm of 1e8 terms (uniform_exponent draws, exponents [-250, 250]; 800 MB)",
     "mean": "exact mean of the 1e8-term uniform_exponent input (800 MB)",
     "f32": "binary32 sum of 2e8 terms (sign, mantissa and exponent in [-60, 60] uniform; 800 MB)",
+    "dot_f32": "binary32 dot product of two 1e8-term vectors (the f32 draws; products exact in binary64; 800 MB read)",
     "serve": "served requests: lengths log-uniform [10, 1e8], slices of a resident 1e8-term uniform_exponent pool, "
              "Poisson arrivals at rho = 0.8 and 2 of the serial service rate",
 }
@@ -231,7 +232,7 @@ def serve_bench(args):
     print(json.dumps(result), flush=True)
 
 
-OPS = ("dot", "sqnorm", "mean", "f32")
+OPS = ("dot", "sqnorm", "mean", "f32", "dot_f32")
 
 
 def op_bench(args):
@@ -251,26 +252,31 @@ def op_bench(args):
         n = 5 * 10 ** 7
         xs = (W.uniform_exponent(n, seed=0, kmin=-250, kmax=250), W.uniform_exponent(n, seed=1, kmin=-250, kmax=250))
         bytes_per_term = 16
-    elif w == "f32":
-        n = 2 * 10 ** 8
-        rng = np.random.default_rng(0)
-        b = ((rng.integers(0, 2, size=n, dtype=np.uint32) << np.uint32(31))
-             | (rng.integers(127 - 60, 127 + 61, size=n, dtype=np.uint32) << np.uint32(23))
-             | rng.integers(0, 1 << 23, size=n, dtype=np.uint32))
-        xs = (b.view(np.float32),)
-        bytes_per_term = 4
+    elif w in ("f32", "dot_f32"):
+        n = 2 * 10 ** 8 if w == "f32" else 10 ** 8
+
+        def f32_draws(seed):
+            rng = np.random.default_rng(seed)
+            b = ((rng.integers(0, 2, size=n, dtype=np.uint32) << np.uint32(31))
+                 | (rng.integers(127 - 60, 127 + 61, size=n, dtype=np.uint32) << np.uint32(23))
+                 | rng.integers(0, 1 << 23, size=n, dtype=np.uint32))
+            return b.view(np.float32)
+        xs = (f32_draws(0),) if w == "f32" else (f32_draws(0), f32_draws(1))
+        bytes_per_term = 4 * len(xs)
     else:
         n = 10 ** 8
         xs = (W.uniform_exponent(n, seed=0, kmin=-250, kmax=250) if w == "sqnorm" else W.uniform_exponent(n, seed=0),)
         bytes_per_term = 8
     bufs = [[torch.from_numpy(a).to(dev) for a in xs] for _ in range(2)]
-    out = torch.empty(1, dtype=torch.float32 if w == "f32" else torch.float64, device=dev)
+    out = torch.empty(1, dtype=torch.float32 if w in ("f32", "dot_f32") else torch.float64, device=dev)
     fn = {"dot": lambda t: ex.exsum_dot_f64(t[0], t[1], out=out, stream=stream),
           "sqnorm": lambda t: ex.exsum_sqnorm_f64(t[0], out=out, stream=stream),
           "mean": lambda t: ex.exsum_mean_f64(t[0], out=out, stream=stream),
-          "f32": lambda t: ex.exsum_f32(t[0], out=out, stream=stream)}[w]
+          "f32": lambda t: ex.exsum_f32(t[0], out=out, stream=stream),
+          "dot_f32": lambda t: ex.exsum_dot_f32(t[0], t[1], out=out, stream=stream)}[w]
     inexact = {"dot": lambda t: torch.dot(t[0], t[1]), "sqnorm": lambda t: torch.dot(t[0], t[0]),
-               "mean": lambda t: torch.mean(t[0]), "f32": lambda t: torch.sum(t[0])}[w]
+               "mean": lambda t: torch.mean(t[0]), "f32": lambda t: torch.sum(t[0]),
+               "dot_f32": lambda t: torch.dot(t[0], t[1])}[w]
     for i in range(args.warmup):
         fn(bufs[i & 1])
     torch.cuda.synchronize()
@@ -284,9 +290,10 @@ def op_bench(args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     avg = ev0.elapsed_time(ev1) / 1e3 / args.steps
-    got = out.cpu().numpy().view(np.uint32 if w == "f32" else np.uint64)[0]
+    got = out.cpu().numpy().view(np.uint32 if w in ("f32", "dot_f32") else np.uint64)[0]
     orc = {"dot": lambda a: oracle.dot_f64(a[0], a[1]), "sqnorm": lambda a: oracle.sqnorm_f64(a[0]),
-           "mean": lambda a: oracle.mean_f64(a[0]), "f32": lambda a: oracle.sum_f32(a[0])}[w]
+           "mean": lambda a: oracle.mean_f64(a[0]), "f32": lambda a: oracle.sum_f32(a[0]),
+           "dot_f32": lambda a: oracle.dot_f32(a[0], a[1])}[w]
     parity = bool(int(got) == int(orc(xs)))
     for i in range(3):
         inexact(bufs[i & 1])
@@ -306,7 +313,7 @@ def op_bench(args):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int64", "data": "synthetic",
-        "config": {"workload": WORKLOADS[w], "tuning": tuning_info(), "n_terms": n, "input_dtype": "f32" if w == "f32" else "f64",
+        "config": {"workload": WORKLOADS[w], "tuning": tuning_info(), "n_terms": n, "input_dtype": "f32" if w in ("f32", "dot_f32") else "f64",
                    "seed": 0, "terms_per_s": round(n * args.steps / wall, 1)},
         "roofline": {"bound": "hbm", "achieved": round(bytes_per_step / avg / 1e9, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(bytes_per_step / avg / 1e9 / HBM_PEAK_GBS, 4), "traffic": None},

@@ -228,6 +228,18 @@ int exsum_mean_f64(const double *x, int64_t n, double *out, void *stream);
    gives +0.  x and out are float device pointers. */
 int exsum_f32(const float *x, int64_t n, float *out, void *stream);
 
+/* out[0] = the exact dot product of two binary32 vectors, rounded once to
+   binary32 (Introduction: the single-precision variant; Performance
+   evaluations: the dot product).  Each product is formed exactly in
+   binary64 (the operands convert exactly, and 24-bit by 24-bit mantissas
+   fit in 53 bits), the products are summed exactly, and the sum is rounded
+   to nearest, ties to even.  Unlike a binary32 sum, a nonzero result can be
+   smaller than half binary32's smallest denormal; it rounds to +0.0, as the
+   mean does.  x and y need not share an alignment.  A NaN product's payload
+   (from the device's binary64 multiply) maps back to binary32 by dropping
+   its 29 low bits. */
+int exsum_dot_f32(const float *x, const float *y, int64_t n, float *out, void *stream);
+
 /* ------------------------------------------------------------------------
  * Streaming, mergeable accumulator (Discussion: parts of a sum are summed
  * separately and their small superaccumulators added).  The state is

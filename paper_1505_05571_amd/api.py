@@ -17,7 +17,8 @@ __all__ = [
     "exsum_get_config", "exsum_set_config", "exsum_release", "exsum_status_string",
     "exsum_autotune", "exsum_load_tuning",
     "ServerConfig", "Server", "exsum_server_default_config", "exsum_server_plan", "exsum_serial_replay",
-    "exsum_sqnorm_f64", "exsum_dot_f64", "exsum_mean_f64", "exsum_f32", "Accumulator", "EXSUM_ACC_BYTES",
+    "exsum_sqnorm_f64", "exsum_dot_f64", "exsum_mean_f64", "exsum_f32", "exsum_dot_f32", "Accumulator",
+    "EXSUM_ACC_BYTES",
     "EXPORTED_SYMBOLS",
 ]
 
@@ -37,7 +38,7 @@ EXPORTED_SYMBOLS = [
     "exsum_server_replay", "exsum_serial_replay", "exsum_server_plan",
     "exsum_sqnorm_f64", "exsum_dot_f64", "exsum_mean_f64", "exsum_f32",
     "exsum_acc_zero", "exsum_acc_add_f64", "exsum_acc_merge", "exsum_acc_round_f64",
-    "exsum_autotune", "exsum_load_tuning",
+    "exsum_autotune", "exsum_load_tuning", "exsum_dot_f32",
 ]
 
 EXSUM_ACC_BYTES = 576
@@ -137,6 +138,8 @@ def load_library():
         lib.exsum_dot_f64.argtypes = [P, P, I64, P, P]
         lib.exsum_mean_f64.argtypes = [P, I64, P, P]
         lib.exsum_f32.argtypes = [P, I64, P, P]
+        lib.exsum_dot_f32.argtypes = [P, P, I64, P, P]
+        lib.exsum_dot_f32.restype = I32
         lib.exsum_acc_zero.argtypes = [P, P]
         lib.exsum_acc_add_f64.argtypes = [P, P, I64, P]
         lib.exsum_acc_merge.argtypes = [P, P, P]
@@ -294,6 +297,22 @@ def exsum_f32(x, out=None, stream=None):
         out = torch.empty(1, dtype=torch.float32, device=x.device)
     out = _dev_f32(out, "out")
     _check(load_library().exsum_f32(_ptr(x), x.numel(), _ptr(out), _stream_handle(stream)), "exsum_f32")
+    return out
+
+
+def exsum_dot_f32(x, y, out=None, stream=None):
+    """Exact dot product of two float32 device tensors (products exact in
+    binary64), rounded once to binary32."""
+    import torch
+    x = _dev_f32(x)
+    y = _dev_f32(y, "y")
+    if y.numel() != x.numel():
+        raise ValueError("x and y differ in length")
+    if out is None:
+        out = torch.empty(1, dtype=torch.float32, device=x.device)
+    out = _dev_f32(out, "out")
+    _check(load_library().exsum_dot_f32(_ptr(x), _ptr(y), x.numel(), _ptr(out), _stream_handle(stream)),
+           "exsum_dot_f32")
     return out
 
 

@@ -293,6 +293,18 @@ int exsum_f32(const float *x, int64_t n, float *out, void *stream) {
   return status_of(launch_f32(x, n, out, w->acc, s, p.grid, p.small, c.precombine));
 }
 
+int exsum_dot_f32(const float *x, const float *y, int64_t n, float *out, void *stream) {
+  if (n < 0 || n >= kMaxN || out == nullptr || (n > 0 && (x == nullptr || y == nullptr))) return EXSUM_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  exsum_config c;
+  Workspace *w = nullptr;
+  int dev = 0;
+  int st = op_setup(s, &c, &w, &dev);
+  if (st != EXSUM_OK) return st;
+  const OpPlan p = plan_op(n, 4, c, dev);
+  return status_of(launch_dot_f32(x, y, n, out, w->acc, s, p.grid, p.small, c.precombine));
+}
+
 int exsum_acc_zero(void *acc, void *stream) {
   if (!acc_ptr_ok(acc)) return EXSUM_EINVAL;
   return status_of(launch_acc_zero(static_cast<GlobalAcc *>(acc), static_cast<hipStream_t>(stream)));

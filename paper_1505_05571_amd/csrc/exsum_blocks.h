@@ -417,6 +417,11 @@ __device__ __forceinline__ unsigned long long f32_to_f64_bits(unsigned int b) {
   const int p = 31 - __clz(m);                       // leading bit of a denormal, 0..22
   return s | ((unsigned long long)(p + 874) << 52) | (((unsigned long long)m << (52 - p)) & ((1ull << 52) - 1));
 }
+// A normal binary32 value (exponent field 1..254) as binary64 bits: the
+// exponent is rebiased by an add and the fraction moves up 29 bits.
+__device__ __forceinline__ unsigned long long f32_normal_to_f64_bits(unsigned int b) {
+  return ((unsigned long long)(b & 0x80000000u) << 32) | ((((unsigned long long)(b & 0x7FFFFFFFu)) << 29) + (896ull << 52));
+}
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 struct SrcF32 {
   const float *x;
@@ -441,12 +446,9 @@ struct SrcF32 {
 #pragma unroll
     for (int k = 0; k < 4; k++) normal &= (((w[k] >> 23) & 255u) - 1u) < 254u;
     if (__all(normal)) {
-      // every term of the wave's vector is a normal number (the common case):
-      // the exponent is rebiased by an add and the fraction moves up 29 bits
+      // every term of the wave's vector is a normal number (the common case)
 #pragma unroll
-      for (int k = 0; k < 4; k++)
-        t[k] = ((unsigned long long)(w[k] & 0x80000000u) << 32) |
-               ((((unsigned long long)(w[k] & 0x7FFFFFFFu)) << 29) + (896ull << 52));
+      for (int k = 0; k < 4; k++) t[k] = f32_normal_to_f64_bits(w[k]);
     } else {
 #pragma unroll
       for (int k = 0; k < 4; k++) t[k] = f32_to_f64_bits(w[k]);
@@ -454,6 +456,79 @@ struct SrcF32 {
   }
   __device__ Raw sload(long long i) const { return __float_as_uint(x[i]); }
   __device__ unsigned long long sterm(Raw r) const { return f32_to_f64_bits(r); }
+};
+
+// Products x[i]*y[i] of binary32 vectors, formed exactly in binary64 (the
+// operands are converted exactly, and 24-bit by 24-bit mantissas fit in 53
+// bits with the exponents in range), for a sum rounded once to binary32.
+// YA: y + a is 16-byte aligned whenever x + a is; otherwise y is read with
+// four 4-byte loads per position.
+template <bool YA>
+struct SrcDotF32 {
+  const float *x;
+  const float *y;
+  static constexpr int kTPV = 4;
+  struct Ptr {
+    const uint4 *p;
+    const float *q;
+  };
+  struct Vec {
+    uint4 a, b;
+  };
+  struct Raw {
+    unsigned int a, b;
+  };
+  __device__ static unsigned long long mul(unsigned long long u, unsigned long long v) {
+    return as_bits(__longlong_as_double((long long)u) * __longlong_as_double((long long)v));
+  }
+  __device__ long long head_terms(long long r0) const {
+    return (long long)(((16u - (unsigned int)(reinterpret_cast<uintptr_t>(x + r0) & 15)) & 15u) >> 2);
+  }
+  __device__ Ptr at(long long a, long long v) const {
+    return Ptr{reinterpret_cast<const uint4 *>(x + a) + v, y + a + 4 * v};
+  }
+  __device__ static Ptr pad() {
+    return Ptr{reinterpret_cast<const uint4 *>(g_pad_tile), reinterpret_cast<const float *>(g_pad_tile)};
+  }
+  __device__ static Vec load(Ptr p, long long k) {
+    Vec r;
+    const u32x4 va = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p.p + k));
+    r.a = make_uint4(va.x, va.y, va.z, va.w);
+    if (YA) {
+      const u32x4 vb = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p.q) + k);
+      r.b = make_uint4(vb.x, vb.y, vb.z, vb.w);
+    } else {
+      const unsigned int *q = reinterpret_cast<const unsigned int *>(p.q) + 4 * k;
+      r.b = make_uint4(__builtin_nontemporal_load(q), __builtin_nontemporal_load(q + 1),
+                       __builtin_nontemporal_load(q + 2), __builtin_nontemporal_load(q + 3));
+    }
+    return r;
+  }
+  __device__ static Vec load_plain(Ptr p, long long k) {
+    Vec r;
+    r.a = p.p[k];
+    const unsigned int *q = reinterpret_cast<const unsigned int *>(p.q) + 4 * k;
+    r.b = make_uint4(q[0], q[1], q[2], q[3]);
+    return r;
+  }
+  __device__ static Vec zero() { return Vec{make_uint4(0u, 0u, 0u, 0u), make_uint4(0u, 0u, 0u, 0u)}; }
+  __device__ void terms(const Vec &v, unsigned long long (&t)[4]) const {
+    const unsigned int wa[4] = {v.a.x, v.a.y, v.a.z, v.a.w};
+    const unsigned int wb[4] = {v.b.x, v.b.y, v.b.z, v.b.w};
+    bool normal = true;
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+      normal &= ((((wa[k] >> 23) & 255u) - 1u) < 254u) & ((((wb[k] >> 23) & 255u) - 1u) < 254u);
+    if (__all(normal)) {
+#pragma unroll
+      for (int k = 0; k < 4; k++) t[k] = mul(f32_normal_to_f64_bits(wa[k]), f32_normal_to_f64_bits(wb[k]));
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; k++) t[k] = mul(f32_to_f64_bits(wa[k]), f32_to_f64_bits(wb[k]));
+    }
+  }
+  __device__ Raw sload(long long i) const { return Raw{__float_as_uint(x[i]), __float_as_uint(y[i])}; }
+  __device__ unsigned long long sterm(Raw r) const { return mul(f32_to_f64_bits(r.a), f32_to_f64_bits(r.b)); }
 };
 
 // Add the source's terms r0 .. r1 into the workgroup's large accumulator.

@@ -48,6 +48,8 @@ hipError_t launch_mean(const double *x, int64_t n, double *out, GlobalAcc *M, hi
                        int precombine);
 hipError_t launch_f32(const float *x, int64_t n, float *out, GlobalAcc *M, hipStream_t s, int grid, bool small,
                       int precombine);
+hipError_t launch_dot_f32(const float *x, const float *y, int64_t n, float *out, GlobalAcc *M, hipStream_t s,
+                          int grid, bool small, int precombine);
 hipError_t launch_acc_add(const double *x, int64_t n, GlobalAcc *acc, GlobalAcc *M, hipStream_t s, int grid,
                           bool small, int precombine);
 hipError_t launch_acc_zero(GlobalAcc *acc, hipStream_t s);

@@ -228,6 +228,7 @@ hipError_t launch_op(const Src &src, int64_t n, const Fin &fin, GlobalAcc *M, hi
 // registers without spilling (measured best of 512x4 and 1024x2 for each).
 constexpr int kDotBlock = 512, kDotVec = 4;      // two inputs per position
 constexpr int kF32Block = 1024, kF32Vec = 2;     // four terms per position
+constexpr int kDotF32Block = 1024, kDotF32Vec = 2;  // four pairs per position
 }  // namespace
 
 hipError_t launch_sqnorm(const double *x, int64_t n, double *out, GlobalAcc *M, hipStream_t s, int grid, bool small,
@@ -250,6 +251,13 @@ hipError_t launch_mean(const double *x, int64_t n, double *out, GlobalAcc *M, hi
 hipError_t launch_f32(const float *x, int64_t n, float *out, GlobalAcc *M, hipStream_t s, int grid, bool small,
                       int precombine) {
   return launch_op<kF32Block, kF32Vec>(SrcF32{x}, n, FinF32{out}, M, s, grid, small, precombine);
+}
+
+hipError_t launch_dot_f32(const float *x, const float *y, int64_t n, float *out, GlobalAcc *M, hipStream_t s,
+                          int grid, bool small, int precombine) {
+  if (((reinterpret_cast<uintptr_t>(x) ^ reinterpret_cast<uintptr_t>(y)) & 15) == 0)
+    return launch_op<kDotF32Block, kDotF32Vec>(SrcDotF32<true>{x, y}, n, FinF32{out}, M, s, grid, small, precombine);
+  return launch_op<kDotF32Block, kDotF32Vec>(SrcDotF32<false>{x, y}, n, FinF32{out}, M, s, grid, small, precombine);
 }
 
 hipError_t launch_acc_add(const double *x, int64_t n, GlobalAcc *acc, GlobalAcc *M, hipStream_t s, int grid,

@@ -202,6 +202,8 @@ def test_further_reductions_host_checks(lib):
     assert lib.exsum_dot_f64(P(8), P(8), 4, None, None) == 1
     assert lib.exsum_mean_f64(P(8), 1 << 40, P(8), None) == 1
     assert lib.exsum_f32(None, 3, P(8), None) == 1
+    assert lib.exsum_dot_f32(P(8), None, 3, P(8), None) == 1
+    assert lib.exsum_dot_f32(P(8), P(8), -1, P(8), None) == 1
     # the accumulator state must be 64-byte aligned device memory
     assert lib.exsum_acc_zero(None, None) == 1
     assert lib.exsum_acc_zero(P(64 + 8), None) == 1

@@ -214,3 +214,50 @@ def test_accumulator_many_updates_and_specials(ex):
     c = ex.Accumulator().add(dev(np.array([1.0, NAN_A])))
     a.merge(c)
     assert u64(a.round()) == int(oracle.sum_f64(np.array([NAN_A])))
+
+
+def test_dot_f32(ex):
+    # random bit patterns (denormals included) and normal-only values, every path
+    for n in SIZES:
+        for x, y in ((f32_bits(n, n + 11), f32_bits(n, n + 12)),
+                     (W.small_normal(n, seed=n).astype(np.float32), W.small_normal(n, seed=n + 1).astype(np.float32))):
+            want = int(oracle.dot_f32(x, y))
+            xt, yt = dev(x), dev(y)
+            for p in paths(ex):
+                assert u32(ex.exsum_dot_f32(xt, yt)) == want, (n, p)
+    # y at another alignment than x (four 4-byte loads per position)
+    x, y = f32_bits(300005, 21), f32_bits(300005, 22)
+    xt, yt = dev(x), dev(y)
+    for lo, hi, d in [(0, 300000, 1), (1, 300001, 2), (3, 299999, 1), (2, 5, 3)]:
+        want = int(oracle.dot_f32(x[lo:hi], y[lo + d:hi + d]))
+        for p in paths(ex):
+            assert u32(ex.exsum_dot_f32(xt[lo:hi], yt[lo + d:hi + d])) == want, (lo, hi, d, p)
+    # closed forms from the oracle's pins, alone and buried in zeros
+    t, u = np.float32(2.0 ** -75), np.float32(2.0 ** -100)
+    fmax = np.finfo(np.float32).max
+    inf = np.float32(np.inf)
+    q = np.array([0x7FC01234], dtype=np.uint32).view(np.float32)[0]
+    cases = [
+        ([t, t, t], [t, t, t], 2),                                  # 3 * 2^-150 -> 2 units
+        ([t], [t], 0),                                              # half a unit, ties to even -> +0
+        ([t, u], [t, u], 1),                                        # just above half a unit
+        ([3.0, -3.0, u], [5.0, 5.0, u], 0),                         # 2^-200 -> +0
+        ([1.0, 2.0 ** -12, u], [1.0, 2.0 ** -12, u], 0x3F800001),   # just above a tie
+        ([fmax, fmax], [2.0, -1.0], int(np.array([fmax]).view(np.uint32)[0])),
+        ([fmax], [2.0], 0x7F800000),
+        ([inf, 1.0], [1.0, 2.0], 0x7F800000),
+        ([inf, inf], [1.0, -1.0], 0x7FC00000),
+        ([q, 1.0], [2.0, 3.0], 0x7FC01234),
+    ]
+    for xs, ys, want in cases:
+        x = np.array(xs, dtype=np.float32)
+        y = np.array(ys, dtype=np.float32)
+        assert int(oracle.dot_f32(x, y)) == want
+        bx = np.zeros(50003, dtype=np.float32)
+        by = np.zeros(50003, dtype=np.float32)
+        pos = np.arange(x.size) * (50003 // x.size)
+        bx[pos], by[pos] = x, y
+        assert int(oracle.dot_f32(bx, by)) == want
+        for p in paths(ex):
+            assert u32(ex.exsum_dot_f32(dev(x), dev(y))) == want, (xs, p)
+            assert u32(ex.exsum_dot_f32(dev(bx), dev(by))) == want, (xs, p)
