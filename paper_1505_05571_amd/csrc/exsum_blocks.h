@@ -658,19 +658,12 @@ __device__ __forceinline__ void final_flush(LargeShared &S) {
 
 // ---------------------------------------------------------------------------
 // Cross-workgroup hand-over.  Everything one workgroup hands to another goes
-// through device-coherent accesses (agent-scope atomic loads, stores and
-// read-modify-writes, which the hardware performs at the device's coherence
-// point rather than in a per-die cache), and each producer waits for its
+// through device-scope atomics (performed at the device's coherence point
+// rather than in a per-die cache), and each producer waits for its
 // accesses to complete before it takes a ticket.  That orders the hand-over
 // without device-wide cache write-back or invalidation (several microseconds
 // each here).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void coherent_store(long long *p, long long v) {
-  __hip_atomic_store((unsigned long long *)p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ long long coherent_load(const long long *p) {
-  return (long long)__hip_atomic_load((const unsigned long long *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 // Wait until this thread's memory operations have completed.
 __device__ __forceinline__ void wait_memory() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
