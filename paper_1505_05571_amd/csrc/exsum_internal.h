@@ -82,9 +82,12 @@ static_assert(sizeof(Piece) == 32, "Piece layout");
 
 // Served pieces (kernels_serve.hip): pieces [0, nshort) have at most
 // short_max terms and are summed one per wavefront; the rest one per
-// workgroup.
-hipError_t launch_pieces(const Piece *pieces, int nshort, int npieces, GlobalAcc *slots, hipStream_t s, int grid,
-                         int precombine);
+// workgroup.  With host_pieces and at most kInlinePieces pieces the list
+// travels in the kernel arguments (`pieces` is then not read); otherwise
+// `pieces` is the device copy of the list.
+constexpr int kInlinePieces = 32;
+hipError_t launch_pieces(const Piece *pieces, const Piece *host_pieces, int nshort, int npieces, GlobalAcc *slots,
+                         hipStream_t s, int grid, int precombine);
 int pieces_block();
 
 }  // namespace exsum

@@ -27,8 +27,19 @@ struct PieceShared {
   unsigned long long wspec[NW][4];
 };
 
-template <int BLOCK, int VEC, int DEPTH>
-__global__ __launch_bounds__(BLOCK) void piece_kernel(const Piece *__restrict__ P, int nshort, int np,
+// The step's piece list: in device memory, or (for a few pieces) in the
+// kernel arguments, which saves a host-to-device copy at low load.
+struct PieceTable {
+  const Piece *p;
+  __device__ Piece operator[](int i) const { return p[i]; }
+};
+struct InlinePieces {
+  Piece p[kInlinePieces];
+  __device__ Piece operator[](int i) const { return p[i]; }
+};
+
+template <int BLOCK, int VEC, int DEPTH, class Table>
+__global__ __launch_bounds__(BLOCK) void piece_kernel(const Table P, int nshort, int np,
                                                       GlobalAcc *__restrict__ slots, int precombine) {
   constexpr int NW = BLOCK / 64;
   __shared__ PieceShared<NW> S;
@@ -69,12 +80,19 @@ constexpr int kPieceBlock = 512;
 
 }  // namespace
 
-hipError_t launch_pieces(const Piece *pieces, int nshort, int npieces, GlobalAcc *slots, hipStream_t s, int grid,
-                         int precombine) {
+hipError_t launch_pieces(const Piece *pieces, const Piece *host_pieces, int nshort, int npieces, GlobalAcc *slots,
+                         hipStream_t s, int grid, int precombine) {
   if (npieces <= 0) return hipSuccess;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL((piece_kernel<kPieceBlock, 4, 2>), dim3(grid), dim3(kPieceBlock), 0, s, pieces, nshort,
-                     npieces, slots, precombine);
+  if (host_pieces != nullptr && npieces <= kInlinePieces) {
+    InlinePieces t;
+    for (int i = 0; i < kInlinePieces; i++) t.p[i] = i < npieces ? host_pieces[i] : Piece{nullptr, 0, nullptr, 0, 0u};
+    hipLaunchKernelGGL((piece_kernel<kPieceBlock, 4, 2, InlinePieces>), dim3(grid), dim3(kPieceBlock), 0, s, t,
+                       nshort, npieces, slots, precombine);
+  } else {
+    hipLaunchKernelGGL((piece_kernel<kPieceBlock, 4, 2, PieceTable>), dim3(grid), dim3(kPieceBlock), 0, s,
+                       PieceTable{pieces}, nshort, npieces, slots, precombine);
+  }
   return hipGetLastError();
 }
 

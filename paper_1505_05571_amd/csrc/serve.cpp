@@ -277,8 +277,12 @@ struct ServerImpl {
     const int want = std::max(nlong, (nshort + per_wg - 1) / per_wg);
     const int grid = std::max(1, std::min(want, grid_cap));
     (void)hipGetLastError();
-    hipError_t e = hipMemcpyAsync(s.dev, s.host, sizeof(Piece) * (size_t)n, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = launch_pieces(s.dev, nshort, n, slots, stream, grid, cfg.precombine);
+    // a few pieces travel in the kernel arguments; more go through the
+    // device copy of the step's table
+    hipError_t e = hipSuccess;
+    if (n > kInlinePieces)
+      e = hipMemcpyAsync(s.dev, s.host, sizeof(Piece) * (size_t)n, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = launch_pieces(s.dev, s.host, nshort, n, slots, stream, grid, cfg.precombine);
     if (e == hipSuccess) e = hipEventRecord(s.ev, stream);
     if (e != hipSuccess) return status_of(e);
     s.finals = finals;
