@@ -114,6 +114,17 @@ def cpu_baseline(x, offsets, budget_s: float = 10.0):
     import oracle
     cores = len(os.sched_getaffinity(0))
     reps, t0 = 0, time.perf_counter()
+    if offsets is None and x.size <= 100000:
+        # a short sum: one call at a time on one core (a latency figure)
+        while True:
+            oracle.sum_f64(x)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= 2.0 or reps >= 100000:
+                break
+        return {"value": round(8.0 * x.size * reps / el / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+                "ms_per_call": round(el / reps * 1e3, 5),
+                "sample": "the full %d-term input, %d calls, one thread" % (x.size, reps)}
     if offsets is None:
         while True:
             oracle.sum_f64_mt(x, cores)
@@ -402,7 +413,7 @@ def main():
 
     # latency of single calls, outside the timed region: device time between
     # events around each call, and host time of call + stream synchronize
-    ncalls = 2000 if n <= 100000 else max(args.steps, 20)
+    ncalls = 10000 if n <= 100000 else max(args.steps, 20)
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(ncalls)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(ncalls)]
     host_ms = np.empty(ncalls)
