@@ -250,3 +250,32 @@ def test_full_size_adversarial(ex):
         x = W.adversarial(1 << 27, seed=0, overflow=ovf)
         want = int(oracle.sum_f64_mt(x, 8))
         assert run(ex, dev(x)) == want
+
+
+def test_beyond_32_bit_indices(ex):
+    # 2^31 + 1000 terms (17 GB on the device, made there): every index and
+    # offset path crosses 2^31.  Closed forms: a sum of ones is its count; a
+    # few planted values change it by exactly their sum.
+    n = (1 << 31) + 1000
+    try:
+        x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    except RuntimeError:
+        pytest.skip("not enough device memory")
+    assert run(ex, x) == int(np.array([float(n)]).view(np.uint64)[0])
+    x[(1 << 31) + 3] = 2.0 ** 60
+    x[5] = -(2.0 ** 60)
+    x[n - 1] = 0.5
+    want = float(n - 3) + 0.5                       # ones at 3 places replaced
+    assert run(ex, x) == int(np.array([want]).view(np.uint64)[0])
+    # segments across the boundary
+    off = np.array([0, (1 << 31) - 5, (1 << 31) + 7, n - 1, n], dtype=np.int64)
+    got = ex.exsum_segmented_f64(x, torch.from_numpy(off).to("cuda:0"))
+    torch.cuda.synchronize()
+    # segment 0 holds -2^60 and 2^31-6 ones, segment 1 holds 2^60 and 11
+    # ones (each a single correctly rounded binary64 addition of exact
+    # operands), segment 2 only ones, segment 3 the half
+    seg = [-(2.0 ** 60) + float((1 << 31) - 6), 2.0 ** 60 + 11.0, float(n - 1 - ((1 << 31) + 7)), 0.5]
+    want_bits = np.array(seg, dtype=np.float64).view(np.uint64)
+    assert np.array_equal(got.cpu().numpy().view(np.uint64), want_bits)
+    del x
+    torch.cuda.empty_cache()
