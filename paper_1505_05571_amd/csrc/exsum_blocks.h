@@ -423,37 +423,11 @@ __device__ __forceinline__ unsigned long long f32_normal_to_f64_bits(unsigned in
   return ((unsigned long long)(b & 0x80000000u) << 32) | ((((unsigned long long)(b & 0x7FFFFFFFu)) << 29) + (896ull << 52));
 }
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+// binary32 terms for the small-only kernel (scalar loads; the large path of
+// binary32 sums is the 512-chunk binary32 accumulator below).
 struct SrcF32 {
   const float *x;
-  static constexpr int kTPV = 4;
-  typedef const uint4 *Ptr;
-  typedef uint4 Vec;
   typedef unsigned int Raw;
-  __device__ long long head_terms(long long r0) const {
-    return (long long)(((16u - (unsigned int)(reinterpret_cast<uintptr_t>(x + r0) & 15)) & 15u) >> 2);
-  }
-  __device__ Ptr at(long long a, long long v) const { return reinterpret_cast<Ptr>(x + a) + v; }
-  __device__ static Ptr pad() { return reinterpret_cast<Ptr>(g_pad_tile); }
-  __device__ static Vec load(Ptr p, long long k) {
-    const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p + k));
-    return make_uint4(v.x, v.y, v.z, v.w);
-  }
-  __device__ static Vec load_plain(Ptr p, long long k) { return p[k]; }
-  __device__ static Vec zero() { return make_uint4(0u, 0u, 0u, 0u); }
-  __device__ void terms(const Vec &v, unsigned long long (&t)[4]) const {
-    const unsigned int w[4] = {v.x, v.y, v.z, v.w};
-    bool normal = true;
-#pragma unroll
-    for (int k = 0; k < 4; k++) normal &= (((w[k] >> 23) & 255u) - 1u) < 254u;
-    if (__all(normal)) {
-      // every term of the wave's vector is a normal number (the common case)
-#pragma unroll
-      for (int k = 0; k < 4; k++) t[k] = f32_normal_to_f64_bits(w[k]);
-    } else {
-#pragma unroll
-      for (int k = 0; k < 4; k++) t[k] = f32_to_f64_bits(w[k]);
-    }
-  }
   __device__ Raw sload(long long i) const { return __float_as_uint(x[i]); }
   __device__ unsigned long long sterm(Raw r) const { return f32_to_f64_bits(r); }
 };
@@ -651,6 +625,186 @@ __device__ __forceinline__ void final_flush(LargeShared &S) {
       atomicAdd((unsigned long long *)&S.small[gi], (unsigned long long)p0);
       atomicAdd((unsigned long long *)&S.small[gi + 1], (unsigned long long)p1);
       atomicAdd((unsigned long long *)&S.small[gi + 2], (unsigned long long)p2);
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// binary32 large superaccumulator.  A binary32 term has an 8-bit exponent
+// field and a 24-bit significand (Formats), so one chunk per (sign, exponent
+// field) makes 512 chunks, and a 64-bit chunk takes 2^40 significands before
+// it can wrap.  A workgroup's range never holds that many terms (the host
+// keeps n below 2^40), so the count bound of the large method
+// (Large superaccumulator) is never reached: the chunks need no counts and no
+// carry checks, every add is a 64-bit LDS add whose old value is not read,
+// and the one transfer into the small accumulator is the final one.
+//
+// A subnormal term has the weight of exponent field 1 and goes to that
+// chunk, so the chunks of exponent field 0 are never read: the fast path
+// adds zeros there (with the implicit bit, like a normal term) instead of
+// branching on them.
+//
+// KC copies of the table, interleaved per chunk (chunk[key * KC + copy], copy
+// = lane mod KC), spread the lanes of one wave that hit the same chunk in the
+// same instruction over KC addresses in different banks; with 8 copies this
+// beats a wave-wide pre-combine even when every term shares one chunk.
+// ---------------------------------------------------------------------------
+constexpr int kF32Keys = 512;
+// Workgroup terms below which no chunk can wrap (checked by the host).
+constexpr long long kF32MaxTermsPerGroup = 1ll << 40;
+
+template <int KC>
+struct F32Shared {
+  unsigned long long chunk[kF32Keys * KC];   // significand sums, chunk[key * KC + copy]
+  long long small[68];                       // the workgroup's small accumulator
+  unsigned long long spec[3];                // +Inf seen, -Inf seen, max NaN bits (binary64 form)
+  unsigned int ticket;
+};
+
+template <int KC>
+__device__ __forceinline__ void f32_init(F32Shared<KC> &S, int tid, int block) {
+  uint4 *p = reinterpret_cast<uint4 *>(&S.chunk[0]);
+  for (int i = tid; i < (int)(sizeof(S.chunk) / 16); i += block) p[i] = make_uint4(0u, 0u, 0u, 0u);
+  if (tid < 68) S.small[tid] = 0;
+  if (tid < 3) S.spec[tid] = 0ull;
+}
+
+// One binary32 term of any class (w: its bits).  Infinities and NaNs go to
+// the side words in their binary64 form; zeros add nothing; a subnormal adds
+// its fraction to the chunk of exponent field 1.
+template <int KC>
+__device__ __forceinline__ void f32_add_any(F32Shared<KC> &S, unsigned int w, unsigned int copy) {
+  const unsigned int e = (w >> 23) & 255u, m = w & 0x7FFFFFu;
+  if (e == 255u) {
+    note_special(f32_to_f64_bits(w), &S.spec[0], &S.spec[1], &S.spec[2]);
+  } else if (e != 0u) {
+    atomicAdd(&S.chunk[(w >> 23) * KC + copy], (unsigned long long)(m | 0x800000u));
+  } else if (m != 0u) {
+    atomicAdd(&S.chunk[((w >> 23) | 1u) * KC + copy], (unsigned long long)m);
+  }
+}
+
+// The NT terms each lane holds, all present.  Common case: every term of the
+// wave is normal or zero (one class test per term), so each term adds its
+// fraction with the implicit bit set to the chunk of its sign and exponent
+// field (zeros to the unread exponent-0 chunks).
+template <int NT, int KC>
+__device__ __forceinline__ void f32_tile(F32Shared<KC> &S, const unsigned int (&w)[NT], int lane) {
+  constexpr int kNormalOrZero = 0x168;   // classes -normal, -0, +0, +normal
+  const unsigned int copy = (unsigned int)lane & (KC - 1);
+  bool plain = true;
+#pragma unroll
+  for (int j = 0; j < NT; j++) plain &= __builtin_amdgcn_classf(__uint_as_float(w[j]), kNormalOrZero);
+  if (__all(plain)) {
+#pragma unroll
+    for (int j = 0; j < NT; j++)
+      atomicAdd(&S.chunk[(w[j] >> 23) * KC + copy], (unsigned long long)((w[j] & 0x7FFFFFu) | 0x800000u));
+  } else {
+#pragma unroll
+    for (int j = 0; j < NT; j++) f32_add_any(S, w[j], copy);
+  }
+}
+
+// Terms [r0, r1) of x into S.  Same geometry as accumulate_range: up to three
+// scalar terms before the first 16-byte boundary and after the last, per-wave
+// contiguous streams of 16-byte positions in tiles of 64*VEC, DEPTH tiles of
+// loads in flight (past-the-end prefetches read the pad tile), and each
+// stream's leftover positions one per lane.
+template <int BLOCK, int VEC, int DEPTH, int KC>
+__device__ __forceinline__ void f32_accumulate_range(F32Shared<KC> &S, const float *__restrict__ x, long long r0,
+                                                     long long r1) {
+  constexpr int NW = BLOCK / 64;
+  constexpr int TILE_W = 64 * VEC;
+  static_assert(VEC <= kMaxVec, "pad tile too small");
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const unsigned int copy = (unsigned int)lane & (KC - 1);
+  if (r1 <= r0) return;
+  long long head = (long long)(((16u - (unsigned int)(reinterpret_cast<uintptr_t>(x + r0) & 15)) & 15u) >> 2);
+  if (head > r1 - r0) head = r1 - r0;
+  const long long a = r0 + head;
+  const long long nv = (r1 - a) / 4;
+  const long long tail = (r1 - a) - nv * 4;
+  const uint4 *__restrict__ xv = reinterpret_cast<const uint4 *>(x + a);
+  const uint4 *pad = reinterpret_cast<const uint4 *>(g_pad_tile);
+  const long long q = nv / NW;
+  const long long ws = (long long)wave * q;
+  const long long we = (wave == NW - 1) ? nv : ws + q;
+  const long long ntiles = q / TILE_W;
+  uint4 buf[DEPTH][VEC];
+  auto load = [&](uint4(&bf)[VEC], long long t) {
+    const uint4 *tp = (t < ntiles) ? xv + ws + t * TILE_W : pad;
+#pragma unroll
+    for (int j = 0; j < VEC; j++) {
+      const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(tp + lane + j * 64));
+      bf[j] = make_uint4(v.x, v.y, v.z, v.w);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  auto process = [&](const uint4(&bf)[VEC]) {
+    unsigned int w[4 * VEC];
+#pragma unroll
+    for (int j = 0; j < VEC; j++) {
+      w[4 * j] = bf[j].x;
+      w[4 * j + 1] = bf[j].y;
+      w[4 * j + 2] = bf[j].z;
+      w[4 * j + 3] = bf[j].w;
+    }
+    f32_tile<4 * VEC, KC>(S, w, lane);
+  };
+  if (ntiles > 0) {
+#pragma unroll
+    for (int d = 0; d < DEPTH; d++) load(buf[d], d);
+    for (long long t = 0; t < ntiles; t += DEPTH) {
+#pragma unroll
+      for (int d = 0; d < DEPTH; d++) {
+        if (d == 0 || t + d < ntiles) process(buf[d]);
+        load(buf[d], t + d + DEPTH);
+      }
+    }
+  }
+  for (long long p = ws + ntiles * TILE_W + lane; p < we; p += 64) {
+    const uint4 v = xv[p];
+    f32_add_any(S, v.x, copy);
+    f32_add_any(S, v.y, copy);
+    f32_add_any(S, v.z, copy);
+    f32_add_any(S, v.w, copy);
+  }
+  if (tid < head) f32_add_any(S, __float_as_uint(x[r0 + tid]), copy);
+  else if (tid < head + tail) f32_add_any(S, __float_as_uint(x[r1 - tail + (tid - head)]), copy);
+}
+
+// Transfer the chunks of exponent fields 1 .. 254 into S.small.  A chunk with
+// exponent field e has weight 2^(e - 150), the weight of the binary64 chunk
+// with exponent field e + 925, so the binary64 transfer applies.  Group h
+// (one wave's iteration) holds the 32 such binary64 exponents with top bits
+// h, of both signs; they span h = 28 .. 36 and land on small chunks
+// h .. h+2.
+template <int BLOCK, int KC>
+__device__ __forceinline__ void f32_final_flush(F32Shared<KC> &S) {
+  constexpr int NW = BLOCK / 64;
+  constexpr int kH0 = (1 + 925) >> 5, kH1 = (254 + 925) >> 5;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __syncthreads();
+  for (int h = kH0 + wave; h <= kH1; h += NW) {
+    const unsigned int sign = (unsigned int)lane >> 5;
+    const int e64 = 32 * h + (lane & 31);
+    const int e = e64 - 925;
+    unsigned long long C = 0;
+    if (e >= 1 && e <= 254) {
+#pragma unroll
+      for (int c = 0; c < KC; c++) C += S.chunk[((sign << 8) | (unsigned int)e) * KC + c];
+    }
+    long long p0 = 0, p1 = 0, p2 = 0;
+    int hh = h;
+    if (C) mantissa_sum_pieces((sign << 11) | (unsigned int)e64, C, p0, p1, p2, hh);
+    p0 = wave_sum_i64(p0);
+    p1 = wave_sum_i64(p1);
+    p2 = wave_sum_i64(p2);
+    if (lane == 0) {
+      atomicAdd((unsigned long long *)&S.small[h], (unsigned long long)p0);
+      atomicAdd((unsigned long long *)&S.small[h + 1], (unsigned long long)p1);
+      atomicAdd((unsigned long long *)&S.small[h + 2], (unsigned long long)p2);
     }
   }
   __syncthreads();

@@ -31,6 +31,23 @@ __global__ __launch_bounds__(BLOCK) void large_kernel(Src src, long long n, Glob
   merge_grid_and_finish(S.small, S.spec, &S.ticket, M, fin);
 }
 
+// binary32 kernel: the same grid and merge as the large kernel, with the
+// 512-chunk binary32 large accumulator (KC interleaved copies) in LDS.
+template <int BLOCK, int VEC, int DEPTH, int KC, class Fin>
+__global__ __launch_bounds__(BLOCK) void f32_kernel(const float *__restrict__ x, long long n,
+                                                    GlobalAcc *__restrict__ M, Fin fin) {
+  __shared__ F32Shared<KC> S;
+  const int tid = threadIdx.x;
+  f32_init(S, tid, BLOCK);
+  __syncthreads();
+  const long long G = gridDim.x;
+  const long long r0 = n * (long long)blockIdx.x / G;
+  const long long r1 = n * (long long)(blockIdx.x + 1) / G;
+  f32_accumulate_range<BLOCK, VEC, DEPTH, KC>(S, x, r0, r1);
+  f32_final_flush<BLOCK, KC>(S);
+  merge_grid_and_finish(S.small, S.spec, &S.ticket, M, fin);
+}
+
 // Small-only kernel: every wavefront sums a contiguous part into its own
 // small superaccumulator; the workgroup adds its wavefronts' accumulators
 // (each below 2^33 per chunk after the final carry step) and merges.
@@ -227,7 +244,6 @@ hipError_t launch_op(const Src &src, int64_t n, const Fin &fin, GlobalAcc *M, hi
 // Sources with more registers per position use shapes that fit their
 // registers without spilling (measured best of 512x4 and 1024x2 for each).
 constexpr int kDotBlock = 512, kDotVec = 4;      // two inputs per position
-constexpr int kF32Block = 1024, kF32Vec = 2;     // four terms per position
 constexpr int kDotF32Block = 1024, kDotF32Vec = 2;  // four pairs per position
 }  // namespace
 
@@ -248,9 +264,24 @@ hipError_t launch_mean(const double *x, int64_t n, double *out, GlobalAcc *M, hi
   return launch_op<kOpBlock, 4>(SrcF64{x}, n, FinMean{out, (unsigned long long)n}, M, s, grid, small, precombine);
 }
 
+// binary32 sums on the large path take the 512-chunk kernel (no pre-combine:
+// its interleaved copies serve a hot chunk better); its chunks cannot wrap
+// while a workgroup's range holds fewer than 2^40 terms, which any n below
+// 2^40 (the entry points' bound) guarantees.
+constexpr int kF32NBlock = 1024, kF32NVec = 4, kF32NDepth = 2, kF32NCopies = 8;
+
 hipError_t launch_f32(const float *x, int64_t n, float *out, GlobalAcc *M, hipStream_t s, int grid, bool small,
                       int precombine) {
-  return launch_op<kF32Block, kF32Vec>(SrcF32{x}, n, FinF32{out}, M, s, grid, small, precombine);
+  if (grid < 1) grid = 1;
+  if (small) {
+    hipLaunchKernelGGL((small_kernel<256, SrcF32, FinF32>), dim3(grid), dim3(256), 0, s, SrcF32{x}, (long long)n, M,
+                       FinF32{out});
+    return hipGetLastError();
+  }
+  if (n >= kF32MaxTermsPerGroup) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((f32_kernel<kF32NBlock, kF32NVec, kF32NDepth, kF32NCopies, FinF32>), dim3(grid),
+                     dim3(kF32NBlock), 0, s, x, (long long)n, M, FinF32{out});
+  return hipGetLastError();
 }
 
 hipError_t launch_dot_f32(const float *x, const float *y, int64_t n, float *out, GlobalAcc *M, hipStream_t s,
@@ -290,7 +321,4 @@ hipError_t launch_inexact(const double *x, int64_t n, double *partials, unsigned
   return hipGetLastError();
 }
 
-}  // namespace exsum
-
-namespace exsum {
 }  // namespace exsum

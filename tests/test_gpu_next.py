@@ -178,6 +178,43 @@ def test_f32(ex):
         assert u32(ex.exsum_f32(xt[lo:hi])) == int(oracle.sum_f32(x[lo:hi])), (lo, hi)
 
 
+def with_config(ex, **kw):
+    c = ex.exsum_get_config()
+    for k, v in kw.items():
+        setattr(c, k, v)
+    ex.exsum_set_config(c)
+
+
+def test_f32_large_accumulator(ex):
+    """The binary32 large path's own cases: whole tiles in one chunk, chunk
+    totals past 2^48, subnormals (added at the weight of exponent field 1),
+    zeros of both signs among normal terms (the fast path's unread chunks),
+    grids with empty or tiny ranges; the pre-combine setting must not
+    matter."""
+    rng = np.random.default_rng(41)
+    one_chunk = (1.0 + rng.random(2_000_003)).astype(np.float32)            # all in [1, 2)
+    heavy = np.full((1 << 25) + 7, np.array([0x3FFFFFFF], dtype=np.uint32).view(np.float32)[0])
+    sub_b = rng.integers(0, 1 << 24, size=1_000_003, dtype=np.uint64).astype(np.uint32)
+    sub_b |= (rng.integers(0, 2, size=sub_b.size, dtype=np.uint64).astype(np.uint32) << np.uint32(31))
+    subnormal_and_e1 = sub_b.view(np.float32)                               # exponent field 0 or 1
+    mixed = f32_bits(100003, 43)
+    with_zeros = rng.standard_normal(1_000_003).astype(np.float32)
+    with_zeros[rng.random(with_zeros.size) < 0.5] = 0.0
+    with_zeros[rng.random(with_zeros.size) < 0.1] = -0.0
+    base = ex.exsum_get_config()
+    try:
+        for x in (one_chunk, heavy, subnormal_and_e1, mixed, with_zeros):
+            want = int(oracle.sum_f32(x))
+            xt = dev(x)
+            for pre in (base.precombine, 0):
+                for grid in (0, 1, 3, 1000):
+                    with_config(ex, small_max=0, precombine=pre, large_grid=grid)
+                    assert u32(ex.exsum_f32(xt)) == want, (x.size, pre, grid)
+            ex.exsum_set_config(base)
+    finally:
+        ex.exsum_set_config(base)
+
+
 def test_accumulator_add_merge_round(ex):
     parts = [W.uniform_exponent(n, seed=20 + n) for n in (0, 1, 1000, 4097, 300001)]
     parts.append(W.adversarial(4000, seed=21))
