@@ -432,74 +432,19 @@ struct SrcF32 {
   __device__ unsigned long long sterm(Raw r) const { return f32_to_f64_bits(r); }
 };
 
-// Products x[i]*y[i] of binary32 vectors, formed exactly in binary64 (the
-// operands are converted exactly, and 24-bit by 24-bit mantissas fit in 53
-// bits with the exponents in range), for a sum rounded once to binary32.
-// YA: y + a is 16-byte aligned whenever x + a is; otherwise y is read with
-// four 4-byte loads per position.
-template <bool YA>
+// Products x[i]*y[i] of binary32 values, formed exactly in binary64 (the
+// operands are converted exactly, and 24-bit by 24-bit significands fit in
+// 53 bits with the exponents in range), for the small-only kernel (scalar
+// loads; the large path of binary32 dot products is the narrow accumulator
+// below).
 struct SrcDotF32 {
   const float *x;
   const float *y;
-  static constexpr int kTPV = 4;
-  struct Ptr {
-    const uint4 *p;
-    const float *q;
-  };
-  struct Vec {
-    uint4 a, b;
-  };
   struct Raw {
     unsigned int a, b;
   };
   __device__ static unsigned long long mul(unsigned long long u, unsigned long long v) {
     return as_bits(__longlong_as_double((long long)u) * __longlong_as_double((long long)v));
-  }
-  __device__ long long head_terms(long long r0) const {
-    return (long long)(((16u - (unsigned int)(reinterpret_cast<uintptr_t>(x + r0) & 15)) & 15u) >> 2);
-  }
-  __device__ Ptr at(long long a, long long v) const {
-    return Ptr{reinterpret_cast<const uint4 *>(x + a) + v, y + a + 4 * v};
-  }
-  __device__ static Ptr pad() {
-    return Ptr{reinterpret_cast<const uint4 *>(g_pad_tile), reinterpret_cast<const float *>(g_pad_tile)};
-  }
-  __device__ static Vec load(Ptr p, long long k) {
-    Vec r;
-    const u32x4 va = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p.p + k));
-    r.a = make_uint4(va.x, va.y, va.z, va.w);
-    if (YA) {
-      const u32x4 vb = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p.q) + k);
-      r.b = make_uint4(vb.x, vb.y, vb.z, vb.w);
-    } else {
-      const unsigned int *q = reinterpret_cast<const unsigned int *>(p.q) + 4 * k;
-      r.b = make_uint4(__builtin_nontemporal_load(q), __builtin_nontemporal_load(q + 1),
-                       __builtin_nontemporal_load(q + 2), __builtin_nontemporal_load(q + 3));
-    }
-    return r;
-  }
-  __device__ static Vec load_plain(Ptr p, long long k) {
-    Vec r;
-    r.a = p.p[k];
-    const unsigned int *q = reinterpret_cast<const unsigned int *>(p.q) + 4 * k;
-    r.b = make_uint4(q[0], q[1], q[2], q[3]);
-    return r;
-  }
-  __device__ static Vec zero() { return Vec{make_uint4(0u, 0u, 0u, 0u), make_uint4(0u, 0u, 0u, 0u)}; }
-  __device__ void terms(const Vec &v, unsigned long long (&t)[4]) const {
-    const unsigned int wa[4] = {v.a.x, v.a.y, v.a.z, v.a.w};
-    const unsigned int wb[4] = {v.b.x, v.b.y, v.b.z, v.b.w};
-    bool normal = true;
-#pragma unroll
-    for (int k = 0; k < 4; k++)
-      normal &= ((((wa[k] >> 23) & 255u) - 1u) < 254u) & ((((wb[k] >> 23) & 255u) - 1u) < 254u);
-    if (__all(normal)) {
-#pragma unroll
-      for (int k = 0; k < 4; k++) t[k] = mul(f32_normal_to_f64_bits(wa[k]), f32_normal_to_f64_bits(wb[k]));
-    } else {
-#pragma unroll
-      for (int k = 0; k < 4; k++) t[k] = mul(f32_to_f64_bits(wa[k]), f32_to_f64_bits(wb[k]));
-    }
   }
   __device__ Raw sload(long long i) const { return Raw{__float_as_uint(x[i]), __float_as_uint(y[i])}; }
   __device__ unsigned long long sterm(Raw r) const { return mul(f32_to_f64_bits(r.a), f32_to_f64_bits(r.b)); }
@@ -631,126 +576,280 @@ __device__ __forceinline__ void final_flush(LargeShared &S) {
 }
 
 // ---------------------------------------------------------------------------
-// binary32 large superaccumulator.  A binary32 term has an 8-bit exponent
-// field and a 24-bit significand (Formats), so one chunk per (sign, exponent
-// field) makes 512 chunks, and a 64-bit chunk takes 2^40 significands before
-// it can wrap.  A workgroup's range never holds that many terms (the host
+// Narrow large superaccumulators for binary32 inputs.  A binary32 term has
+// an 8-bit exponent field and a 24-bit significand (Formats), so one chunk
+// per (sign, exponent field) makes 512 chunks, and a 64-bit chunk takes 2^40
+// significands before it can wrap.  An exact product of two binary32 values
+// has a 48-bit significand; split into two 24-bit halves, added to the
+// chunks of its exponent and of its exponent + 24, it fits the same scheme
+// with 2 x 536 chunks.  A workgroup's range never holds 2^40 terms (the host
 // keeps n below 2^40), so the count bound of the large method
-// (Large superaccumulator) is never reached: the chunks need no counts and no
-// carry checks, every add is a 64-bit LDS add whose old value is not read,
+// (Large superaccumulator) is never reached: the chunks need no counts and
+// no carry checks, every add is a 64-bit LDS add whose old value is not read,
 // and the one transfer into the small accumulator is the final one.
-//
-// A subnormal term has the weight of exponent field 1 and goes to that
-// chunk, so the chunks of exponent field 0 are never read: the fast path
-// adds zeros there (with the implicit bit, like a normal term) instead of
-// branching on them.
 //
 // KC copies of the table, interleaved per chunk (chunk[key * KC + copy], copy
 // = lane mod KC), spread the lanes of one wave that hit the same chunk in the
 // same instruction over KC addresses in different banks; with 8 copies this
 // beats a wave-wide pre-combine even when every term shares one chunk.
+//
+// A term kind T gives: the chunks per sign (kKeysPerSign, key = sign *
+// kKeysPerSign + k), the k that the transfer reads (kKeyLo .. kKeyHi), the
+// binary64 exponent field of the same weight as k (k + kExpOffset), the
+// vector interface of the term sources above (head_terms, at, pad, load,
+// load_plain), tile() for a tile of present terms, add_vec() for one
+// position of any class and add_scalar() for one scalar term.
 // ---------------------------------------------------------------------------
-constexpr int kF32Keys = 512;
-// Workgroup terms below which no chunk can wrap (checked by the host).
-constexpr long long kF32MaxTermsPerGroup = 1ll << 40;
+// Terms below which no chunk can wrap (checked by the host).
+constexpr long long kNarrowMaxTerms = 1ll << 40;
 
-template <int KC>
-struct F32Shared {
-  unsigned long long chunk[kF32Keys * KC];   // significand sums, chunk[key * KC + copy]
+template <int KEYS, int KC>
+struct NarrowShared {
+  unsigned long long chunk[KEYS * KC];       // sums of 24-bit pieces, chunk[key * KC + copy]
   long long small[68];                       // the workgroup's small accumulator
   unsigned long long spec[3];                // +Inf seen, -Inf seen, max NaN bits (binary64 form)
   unsigned int ticket;
 };
 
-template <int KC>
-__device__ __forceinline__ void f32_init(F32Shared<KC> &S, int tid, int block) {
+template <int KEYS, int KC>
+__device__ __forceinline__ void narrow_init(NarrowShared<KEYS, KC> &S, int tid, int block) {
   uint4 *p = reinterpret_cast<uint4 *>(&S.chunk[0]);
   for (int i = tid; i < (int)(sizeof(S.chunk) / 16); i += block) p[i] = make_uint4(0u, 0u, 0u, 0u);
   if (tid < 68) S.small[tid] = 0;
   if (tid < 3) S.spec[tid] = 0ull;
 }
 
-// One binary32 term of any class (w: its bits).  Infinities and NaNs go to
-// the side words in their binary64 form; zeros add nothing; a subnormal adds
-// its fraction to the chunk of exponent field 1.
-template <int KC>
-__device__ __forceinline__ void f32_add_any(F32Shared<KC> &S, unsigned int w, unsigned int copy) {
-  const unsigned int e = (w >> 23) & 255u, m = w & 0x7FFFFFu;
-  if (e == 255u) {
-    note_special(f32_to_f64_bits(w), &S.spec[0], &S.spec[1], &S.spec[2]);
-  } else if (e != 0u) {
-    atomicAdd(&S.chunk[(w >> 23) * KC + copy], (unsigned long long)(m | 0x800000u));
-  } else if (m != 0u) {
-    atomicAdd(&S.chunk[((w >> 23) | 1u) * KC + copy], (unsigned long long)m);
-  }
+// Which of the classes -normal, -0, +0, +normal (v_cmp_class) a value is in.
+__device__ __forceinline__ bool f32_normal_or_zero(unsigned int w) {
+  return __builtin_amdgcn_classf(__uint_as_float(w), 0x168);
+}
+__device__ __forceinline__ bool f32_normal(unsigned int w) {
+  return __builtin_amdgcn_classf(__uint_as_float(w), 0x108);
 }
 
-// The NT terms each lane holds, all present.  Common case: every term of the
-// wave is normal or zero (one class test per term), so each term adds its
-// fraction with the implicit bit set to the chunk of its sign and exponent
-// field (zeros to the unread exponent-0 chunks).
-template <int NT, int KC>
-__device__ __forceinline__ void f32_tile(F32Shared<KC> &S, const unsigned int (&w)[NT], int lane) {
-  constexpr int kNormalOrZero = 0x168;   // classes -normal, -0, +0, +normal
-  const unsigned int copy = (unsigned int)lane & (KC - 1);
-  bool plain = true;
-#pragma unroll
-  for (int j = 0; j < NT; j++) plain &= __builtin_amdgcn_classf(__uint_as_float(w[j]), kNormalOrZero);
-  if (__all(plain)) {
-#pragma unroll
-    for (int j = 0; j < NT; j++)
-      atomicAdd(&S.chunk[(w[j] >> 23) * KC + copy], (unsigned long long)((w[j] & 0x7FFFFFu) | 0x800000u));
-  } else {
-#pragma unroll
-    for (int j = 0; j < NT; j++) f32_add_any(S, w[j], copy);
+// binary32 sum terms.  Key k is the exponent field.  A subnormal term has
+// the weight of exponent field 1 and goes to that chunk, so the chunks of
+// exponent field 0 are never read: the fast path adds zeros there (with the
+// implicit bit, like a normal term) instead of branching on them.
+struct NarrowSumF32 {
+  static constexpr int kKeysPerSign = 256, kKeyLo = 1, kKeyHi = 254, kExpOffset = 925;
+  static constexpr int kKeys = 2 * kKeysPerSign;
+  const float *x;
+  typedef const uint4 *Ptr;
+  typedef uint4 Vec;
+  __device__ long long head_terms(long long r0) const {
+    return (long long)(((16u - (unsigned int)(reinterpret_cast<uintptr_t>(x + r0) & 15)) & 15u) >> 2);
   }
-}
+  __device__ Ptr at(long long a, long long v) const { return reinterpret_cast<Ptr>(x + a) + v; }
+  __device__ static Ptr pad() { return reinterpret_cast<Ptr>(g_pad_tile); }
+  __device__ static Vec load(Ptr p, long long k) {
+    const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p + k));
+    return make_uint4(v.x, v.y, v.z, v.w);
+  }
+  __device__ static Vec load_plain(Ptr p, long long k) { return p[k]; }
+  // one term of any class: infinities and NaNs go to the side words in
+  // their binary64 form; zeros add nothing
+  template <int KC>
+  __device__ static void add_any(NarrowShared<kKeys, KC> &S, unsigned int w, unsigned int copy) {
+    const unsigned int e = (w >> 23) & 255u, m = w & 0x7FFFFFu;
+    if (e == 255u) {
+      note_special(f32_to_f64_bits(w), &S.spec[0], &S.spec[1], &S.spec[2]);
+    } else if (e != 0u) {
+      atomicAdd(&S.chunk[(w >> 23) * KC + copy], (unsigned long long)(m | 0x800000u));
+    } else if (m != 0u) {
+      atomicAdd(&S.chunk[((w >> 23) | 1u) * KC + copy], (unsigned long long)m);
+    }
+  }
+  template <int KC>
+  __device__ static void add_vec(NarrowShared<kKeys, KC> &S, const Vec &v, unsigned int copy) {
+    add_any(S, v.x, copy);
+    add_any(S, v.y, copy);
+    add_any(S, v.z, copy);
+    add_any(S, v.w, copy);
+  }
+  template <int KC>
+  __device__ void add_scalar(NarrowShared<kKeys, KC> &S, long long i, unsigned int copy) const {
+    add_any(S, __float_as_uint(x[i]), copy);
+  }
+  // Common case: every term of the wave is normal or zero (one class test
+  // per term); each adds its fraction with the implicit bit set to the
+  // chunk of its sign and exponent field.
+  template <int VEC, int KC>
+  __device__ static void tile(NarrowShared<kKeys, KC> &S, const Vec (&v)[VEC], int lane) {
+    const unsigned int copy = (unsigned int)lane & (KC - 1);
+    unsigned int w[4 * VEC];
+#pragma unroll
+    for (int j = 0; j < VEC; j++) {
+      w[4 * j] = v[j].x;
+      w[4 * j + 1] = v[j].y;
+      w[4 * j + 2] = v[j].z;
+      w[4 * j + 3] = v[j].w;
+    }
+    bool plain = true;
+#pragma unroll
+    for (int j = 0; j < 4 * VEC; j++) plain &= f32_normal_or_zero(w[j]);
+    if (__all(plain)) {
+#pragma unroll
+      for (int j = 0; j < 4 * VEC; j++)
+        atomicAdd(&S.chunk[(w[j] >> 23) * KC + copy], (unsigned long long)((w[j] & 0x7FFFFFu) | 0x800000u));
+    } else {
+#pragma unroll
+      for (int j = 0; j < VEC; j++) add_vec(S, v[j], copy);
+    }
+  }
+};
 
-// Terms [r0, r1) of x into S.  Same geometry as accumulate_range: up to three
-// scalar terms before the first 16-byte boundary and after the last, per-wave
-// contiguous streams of 16-byte positions in tiles of 64*VEC, DEPTH tiles of
-// loads in flight (past-the-end prefetches read the pad tile), and each
-// stream's leftover positions one per lane.
-template <int BLOCK, int VEC, int DEPTH, int KC>
-__device__ __forceinline__ void f32_accumulate_range(F32Shared<KC> &S, const float *__restrict__ x, long long r0,
-                                                     long long r1) {
+// binary32 dot-product terms.  The product of x = (-1)^sx Mx 2^(ex-150) and
+// y = (-1)^sy My 2^(ey-150) (M with the implicit bit, e the exponent field,
+// raised to 1 for subnormals) is (-1)^(sx^sy) P 2^(k-300), P = Mx My < 2^48,
+// k = ex + ey in 2 .. 508: the low 24 bits of P go to key (sx^sy, k) and the
+// high 24 bits to key (sx^sy, k + 24), which has weight 2^24 more.  The
+// product is exact (Formats), so any infinity or NaN among the operands
+// makes it an infinity or NaN, recorded in its binary64 form (the operands'
+// binary64 product).  YA: y + a is 16-byte aligned whenever x + a is;
+// otherwise y is read with four 4-byte loads per position.
+template <bool YA>
+struct NarrowDotF32 {
+  static constexpr int kKeysPerSign = 536, kKeyLo = 2, kKeyHi = 532, kExpOffset = 775;
+  static constexpr int kKeys = 2 * kKeysPerSign;
+  const float *x;
+  const float *y;
+  struct Ptr {
+    const uint4 *p;
+    const float *q;
+  };
+  struct Vec {
+    uint4 a, b;
+  };
+  __device__ long long head_terms(long long r0) const {
+    return (long long)(((16u - (unsigned int)(reinterpret_cast<uintptr_t>(x + r0) & 15)) & 15u) >> 2);
+  }
+  __device__ Ptr at(long long a, long long v) const {
+    return Ptr{reinterpret_cast<const uint4 *>(x + a) + v, y + a + 4 * v};
+  }
+  __device__ static Ptr pad() {
+    return Ptr{reinterpret_cast<const uint4 *>(g_pad_tile), reinterpret_cast<const float *>(g_pad_tile)};
+  }
+  __device__ static Vec load(Ptr p, long long k) {
+    Vec r;
+    const u32x4 va = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p.p + k));
+    r.a = make_uint4(va.x, va.y, va.z, va.w);
+    if (YA) {
+      const u32x4 vb = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p.q) + k);
+      r.b = make_uint4(vb.x, vb.y, vb.z, vb.w);
+    } else {
+      const unsigned int *q = reinterpret_cast<const unsigned int *>(p.q) + 4 * k;
+      r.b = make_uint4(__builtin_nontemporal_load(q), __builtin_nontemporal_load(q + 1),
+                       __builtin_nontemporal_load(q + 2), __builtin_nontemporal_load(q + 3));
+    }
+    return r;
+  }
+  __device__ static Vec load_plain(Ptr p, long long k) {
+    Vec r;
+    r.a = p.p[k];
+    const unsigned int *q = reinterpret_cast<const unsigned int *>(p.q) + 4 * k;
+    r.b = make_uint4(q[0], q[1], q[2], q[3]);
+    return r;
+  }
+  // add P's two halves for key base kb (sign * kKeysPerSign + k)
+  template <int KC>
+  __device__ static void add_product(NarrowShared<kKeys, KC> &S, unsigned int kb, unsigned int mx, unsigned int my,
+                                     unsigned int copy) {
+    const unsigned long long P = (unsigned long long)mx * my;          // below 2^48
+    unsigned long long *c = &S.chunk[kb * KC + copy];
+    atomicAdd(c, P & 0xFFFFFFull);
+    atomicAdd(c + 24 * KC, P >> 24);
+  }
+  // one pair of any class
+  template <int KC>
+  __device__ static void add_pair(NarrowShared<kKeys, KC> &S, unsigned int wx, unsigned int wy, unsigned int copy) {
+    const unsigned int ex = (wx >> 23) & 255u, ey = (wy >> 23) & 255u;
+    if (ex == 255u || ey == 255u) {
+      note_special(as_bits(__longlong_as_double((long long)f32_to_f64_bits(wx)) *
+                           __longlong_as_double((long long)f32_to_f64_bits(wy))),
+                   &S.spec[0], &S.spec[1], &S.spec[2]);
+      return;
+    }
+    const unsigned int mx = (wx & 0x7FFFFFu) | (ex ? 0x800000u : 0u);
+    const unsigned int my = (wy & 0x7FFFFFu) | (ey ? 0x800000u : 0u);
+    if (mx == 0u || my == 0u) return;                                  // a zero product
+    const unsigned int k = (ex ? ex : 1u) + (ey ? ey : 1u);
+    add_product(S, ((wx ^ wy) >> 31) * kKeysPerSign + k, mx, my, copy);
+  }
+  template <int KC>
+  __device__ static void add_vec(NarrowShared<kKeys, KC> &S, const Vec &v, unsigned int copy) {
+    add_pair(S, v.a.x, v.b.x, copy);
+    add_pair(S, v.a.y, v.b.y, copy);
+    add_pair(S, v.a.z, v.b.z, copy);
+    add_pair(S, v.a.w, v.b.w, copy);
+  }
+  template <int KC>
+  __device__ void add_scalar(NarrowShared<kKeys, KC> &S, long long i, unsigned int copy) const {
+    add_pair(S, __float_as_uint(x[i]), __float_as_uint(y[i]), copy);
+  }
+  // Common case: every operand in the wave is a normal number (one class
+  // test each).
+  template <int VEC, int KC>
+  __device__ static void tile(NarrowShared<kKeys, KC> &S, const Vec (&v)[VEC], int lane) {
+    const unsigned int copy = (unsigned int)lane & (KC - 1);
+    unsigned int wx[4 * VEC], wy[4 * VEC];
+#pragma unroll
+    for (int j = 0; j < VEC; j++) {
+      wx[4 * j] = v[j].a.x;
+      wx[4 * j + 1] = v[j].a.y;
+      wx[4 * j + 2] = v[j].a.z;
+      wx[4 * j + 3] = v[j].a.w;
+      wy[4 * j] = v[j].b.x;
+      wy[4 * j + 1] = v[j].b.y;
+      wy[4 * j + 2] = v[j].b.z;
+      wy[4 * j + 3] = v[j].b.w;
+    }
+    bool normal = true;
+#pragma unroll
+    for (int j = 0; j < 4 * VEC; j++) normal &= f32_normal(wx[j]) && f32_normal(wy[j]);
+    if (__all(normal)) {
+#pragma unroll
+      for (int j = 0; j < 4 * VEC; j++) {
+        const unsigned int k = ((wx[j] >> 23) & 255u) + ((wy[j] >> 23) & 255u);
+        add_product(S, ((wx[j] ^ wy[j]) >> 31) * kKeysPerSign + k, (wx[j] & 0x7FFFFFu) | 0x800000u,
+                    (wy[j] & 0x7FFFFFu) | 0x800000u, copy);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < VEC; j++) add_vec(S, v[j], copy);
+    }
+  }
+};
+
+// Terms [r0, r1) of the source into S.  Same geometry as accumulate_range:
+// up to three scalar terms before the first 16-byte boundary and after the
+// last, per-wave contiguous streams of 16-byte positions in tiles of 64*VEC,
+// DEPTH tiles of loads in flight (past-the-end prefetches read the pad
+// tile), and each stream's leftover positions one per lane.
+template <int BLOCK, int VEC, int DEPTH, int KC, class T>
+__device__ __forceinline__ void narrow_accumulate_range(NarrowShared<T::kKeys, KC> &S, const T &src, long long r0,
+                                                        long long r1) {
   constexpr int NW = BLOCK / 64;
   constexpr int TILE_W = 64 * VEC;
   static_assert(VEC <= kMaxVec, "pad tile too small");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const unsigned int copy = (unsigned int)lane & (KC - 1);
   if (r1 <= r0) return;
-  long long head = (long long)(((16u - (unsigned int)(reinterpret_cast<uintptr_t>(x + r0) & 15)) & 15u) >> 2);
+  long long head = src.head_terms(r0);
   if (head > r1 - r0) head = r1 - r0;
   const long long a = r0 + head;
   const long long nv = (r1 - a) / 4;
   const long long tail = (r1 - a) - nv * 4;
-  const uint4 *__restrict__ xv = reinterpret_cast<const uint4 *>(x + a);
-  const uint4 *pad = reinterpret_cast<const uint4 *>(g_pad_tile);
   const long long q = nv / NW;
   const long long ws = (long long)wave * q;
   const long long we = (wave == NW - 1) ? nv : ws + q;
   const long long ntiles = q / TILE_W;
-  uint4 buf[DEPTH][VEC];
-  auto load = [&](uint4(&bf)[VEC], long long t) {
-    const uint4 *tp = (t < ntiles) ? xv + ws + t * TILE_W : pad;
+  typename T::Vec buf[DEPTH][VEC];
+  auto load = [&](typename T::Vec(&bf)[VEC], long long t) {
+    const typename T::Ptr tp = (t < ntiles) ? src.at(a, ws + t * TILE_W) : T::pad();
 #pragma unroll
-    for (int j = 0; j < VEC; j++) {
-      const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(tp + lane + j * 64));
-      bf[j] = make_uint4(v.x, v.y, v.z, v.w);
-    }
+    for (int j = 0; j < VEC; j++) bf[j] = T::load(tp, lane + j * 64);
     __builtin_amdgcn_sched_barrier(0);
-  };
-  auto process = [&](const uint4(&bf)[VEC]) {
-    unsigned int w[4 * VEC];
-#pragma unroll
-    for (int j = 0; j < VEC; j++) {
-      w[4 * j] = bf[j].x;
-      w[4 * j + 1] = bf[j].y;
-      w[4 * j + 2] = bf[j].z;
-      w[4 * j + 3] = bf[j].w;
-    }
-    f32_tile<4 * VEC, KC>(S, w, lane);
   };
   if (ntiles > 0) {
 #pragma unroll
@@ -758,42 +857,37 @@ __device__ __forceinline__ void f32_accumulate_range(F32Shared<KC> &S, const flo
     for (long long t = 0; t < ntiles; t += DEPTH) {
 #pragma unroll
       for (int d = 0; d < DEPTH; d++) {
-        if (d == 0 || t + d < ntiles) process(buf[d]);
+        if (d == 0 || t + d < ntiles) T::template tile<VEC, KC>(S, buf[d], lane);
         load(buf[d], t + d + DEPTH);
       }
     }
   }
-  for (long long p = ws + ntiles * TILE_W + lane; p < we; p += 64) {
-    const uint4 v = xv[p];
-    f32_add_any(S, v.x, copy);
-    f32_add_any(S, v.y, copy);
-    f32_add_any(S, v.z, copy);
-    f32_add_any(S, v.w, copy);
-  }
-  if (tid < head) f32_add_any(S, __float_as_uint(x[r0 + tid]), copy);
-  else if (tid < head + tail) f32_add_any(S, __float_as_uint(x[r1 - tail + (tid - head)]), copy);
+  const typename T::Ptr base = src.at(a, 0);
+  for (long long p = ws + ntiles * TILE_W + lane; p < we; p += 64) T::add_vec(S, T::load_plain(base, p), copy);
+  if (tid < head) src.add_scalar(S, r0 + tid, copy);
+  else if (tid < head + tail) src.add_scalar(S, r1 - tail + (tid - head), copy);
 }
 
-// Transfer the chunks of exponent fields 1 .. 254 into S.small.  A chunk with
-// exponent field e has weight 2^(e - 150), the weight of the binary64 chunk
-// with exponent field e + 925, so the binary64 transfer applies.  Group h
-// (one wave's iteration) holds the 32 such binary64 exponents with top bits
-// h, of both signs; they span h = 28 .. 36 and land on small chunks
-// h .. h+2.
-template <int BLOCK, int KC>
-__device__ __forceinline__ void f32_final_flush(F32Shared<KC> &S) {
+// Transfer the chunks with k in kKeyLo .. kKeyHi into S.small.  Chunk k has
+// the weight of the binary64 chunk with exponent field k + kExpOffset, so the
+// binary64 transfer applies.  Group h (one wave's iteration) holds the 32
+// such binary64 exponents with top bits h, of both signs, which land on
+// small chunks h .. h+2.
+template <int BLOCK, int KC, class T>
+__device__ __forceinline__ void narrow_final_flush(NarrowShared<T::kKeys, KC> &S) {
   constexpr int NW = BLOCK / 64;
-  constexpr int kH0 = (1 + 925) >> 5, kH1 = (254 + 925) >> 5;
+  constexpr int kH0 = (T::kKeyLo + T::kExpOffset) >> 5, kH1 = (T::kKeyHi + T::kExpOffset) >> 5;
+  static_assert(kH1 + 2 < 68 && T::kKeyHi + T::kExpOffset < 2047, "transfer range");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   __syncthreads();
   for (int h = kH0 + wave; h <= kH1; h += NW) {
     const unsigned int sign = (unsigned int)lane >> 5;
     const int e64 = 32 * h + (lane & 31);
-    const int e = e64 - 925;
+    const int k = e64 - T::kExpOffset;
     unsigned long long C = 0;
-    if (e >= 1 && e <= 254) {
+    if (k >= T::kKeyLo && k <= T::kKeyHi) {
 #pragma unroll
-      for (int c = 0; c < KC; c++) C += S.chunk[((sign << 8) | (unsigned int)e) * KC + c];
+      for (int c = 0; c < KC; c++) C += S.chunk[(sign * T::kKeysPerSign + (unsigned int)k) * KC + c];
     }
     long long p0 = 0, p1 = 0, p2 = 0;
     int hh = h;
@@ -1070,11 +1164,15 @@ __device__ __forceinline__ void small_carry_all(long long *acc, int lane) {
 }
 
 // Wave adds the source's terms lo .. hi into acc (small_acc_words<COPIES>()
-// words, zeroed by the caller); specials into spec[3].  On return the sum is in the first 68
-// words, each below COPIES * 2^33 in magnitude.
+// words, zeroed by the caller); specials into spec[3].  On return the sum is
+// in the first 68 words, each below COPIES * 2^33 in magnitude.  With
+// `direct` (the caller rounds the result and merges it nowhere), a range of
+// fewer than 1024 terms skips the carry steps of the copies: every term adds
+// at most one piece below 2^52 to a given chunk, so each chunk's total over
+// all copies stays below 1023 * 2^52 < 2^62, which the rounding accepts.
 template <int COPIES, class Src>
 __device__ __forceinline__ void small_wave_accumulate(long long *acc, unsigned long long *spec, const Src &src,
-                                                      long long lo, long long hi, int lane) {
+                                                      long long lo, long long hi, int lane, bool direct = false) {
   // a copy's chunk receives at most 64 / COPIES pieces below 2^52 per
   // 64-term step; a carry step after every kEvery batches keeps it below
   // 1536 * 2^52 < 2^63
@@ -1106,7 +1204,7 @@ __device__ __forceinline__ void small_wave_accumulate(long long *acc, unsigned l
       if (base >= hi) break;
     }
   }
-  small_carry_all<COPIES>(acc, lane);
+  if (!(direct && hi - lo < 1024)) small_carry_all<COPIES>(acc, lane);
   if (COPIES > 1) {
     // add the copies into the first: every copy is below 2^33 after its carry
     __builtin_amdgcn_wave_barrier();

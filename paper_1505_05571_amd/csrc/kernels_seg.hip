@@ -333,7 +333,7 @@ __global__ __launch_bounds__(BLOCK) void seg_short_kernel(const double *__restri
       const int j = __builtin_amdgcn_readfirstlane(S.ord[k]);
       const long long a = uniform_i64(S.lo[j]), b = uniform_i64(S.hi[j]);
       small_wave_zero<kShortCopies>(acc, spec, lane);
-      small_wave_accumulate<kShortCopies>(acc, spec, SrcF64{x}, a, b, lane);
+      small_wave_accumulate<kShortCopies>(acc, spec, SrcF64{x}, a, b, lane, true);
       wave_merge_and_round(acc, spec, nullptr, 1u, &out[r0 + j], lane);
     }
     __syncthreads();

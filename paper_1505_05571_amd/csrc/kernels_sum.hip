@@ -31,20 +31,20 @@ __global__ __launch_bounds__(BLOCK) void large_kernel(Src src, long long n, Glob
   merge_grid_and_finish(S.small, S.spec, &S.ticket, M, fin);
 }
 
-// binary32 kernel: the same grid and merge as the large kernel, with the
-// 512-chunk binary32 large accumulator (KC interleaved copies) in LDS.
-template <int BLOCK, int VEC, int DEPTH, int KC, class Fin>
-__global__ __launch_bounds__(BLOCK) void f32_kernel(const float *__restrict__ x, long long n,
-                                                    GlobalAcc *__restrict__ M, Fin fin) {
-  __shared__ F32Shared<KC> S;
+// Narrow kernel (binary32 sums and dot products): the same grid and merge
+// as the large kernel, with a narrow large accumulator (KC interleaved
+// copies) in LDS.
+template <int BLOCK, int VEC, int DEPTH, int KC, class T, class Fin>
+__global__ __launch_bounds__(BLOCK) void narrow_kernel(T src, long long n, GlobalAcc *__restrict__ M, Fin fin) {
+  __shared__ NarrowShared<T::kKeys, KC> S;
   const int tid = threadIdx.x;
-  f32_init(S, tid, BLOCK);
+  narrow_init(S, tid, BLOCK);
   __syncthreads();
   const long long G = gridDim.x;
   const long long r0 = n * (long long)blockIdx.x / G;
   const long long r1 = n * (long long)(blockIdx.x + 1) / G;
-  f32_accumulate_range<BLOCK, VEC, DEPTH, KC>(S, x, r0, r1);
-  f32_final_flush<BLOCK, KC>(S);
+  narrow_accumulate_range<BLOCK, VEC, DEPTH, KC>(S, src, r0, r1);
+  narrow_final_flush<BLOCK, KC, T>(S);
   merge_grid_and_finish(S.small, S.spec, &S.ticket, M, fin);
 }
 
@@ -244,7 +244,6 @@ hipError_t launch_op(const Src &src, int64_t n, const Fin &fin, GlobalAcc *M, hi
 // Sources with more registers per position use shapes that fit their
 // registers without spilling (measured best of 512x4 and 1024x2 for each).
 constexpr int kDotBlock = 512, kDotVec = 4;      // two inputs per position
-constexpr int kDotF32Block = 1024, kDotF32Vec = 2;  // four pairs per position
 }  // namespace
 
 hipError_t launch_sqnorm(const double *x, int64_t n, double *out, GlobalAcc *M, hipStream_t s, int grid, bool small,
@@ -264,31 +263,44 @@ hipError_t launch_mean(const double *x, int64_t n, double *out, GlobalAcc *M, hi
   return launch_op<kOpBlock, 4>(SrcF64{x}, n, FinMean{out, (unsigned long long)n}, M, s, grid, small, precombine);
 }
 
-// binary32 sums on the large path take the 512-chunk kernel (no pre-combine:
-// its interleaved copies serve a hot chunk better); its chunks cannot wrap
-// while a workgroup's range holds fewer than 2^40 terms, which any n below
-// 2^40 (the entry points' bound) guarantees.
-constexpr int kF32NBlock = 1024, kF32NVec = 4, kF32NDepth = 2, kF32NCopies = 8;
+// binary32 sums and dot products on the large path take the narrow kernel
+// (no pre-combine: its interleaved copies serve a hot chunk better); its
+// chunks cannot wrap while a workgroup's range holds fewer than 2^40 terms,
+// which any n below 2^40 (the entry points' bound) guarantees.
+constexpr int kNarrowBlock = 1024, kNarrowVec = 4, kNarrowDepth = 2, kNarrowCopies = 8;
+constexpr int kNarrowDotVec = 2;
+
+template <class T>
+hipError_t launch_narrow(const T &src, int64_t n, float *out, GlobalAcc *M, hipStream_t s, int grid) {
+  if (n >= kNarrowMaxTerms) return hipErrorInvalidValue;
+  constexpr int VEC = sizeof(typename T::Vec) > 16 ? kNarrowDotVec : kNarrowVec;
+  hipLaunchKernelGGL((narrow_kernel<kNarrowBlock, VEC, kNarrowDepth, kNarrowCopies, T, FinF32>), dim3(grid),
+                     dim3(kNarrowBlock), 0, s, src, (long long)n, M, FinF32{out});
+  return hipGetLastError();
+}
 
 hipError_t launch_f32(const float *x, int64_t n, float *out, GlobalAcc *M, hipStream_t s, int grid, bool small,
-                      int precombine) {
+                      int) {
   if (grid < 1) grid = 1;
   if (small) {
     hipLaunchKernelGGL((small_kernel<256, SrcF32, FinF32>), dim3(grid), dim3(256), 0, s, SrcF32{x}, (long long)n, M,
                        FinF32{out});
     return hipGetLastError();
   }
-  if (n >= kF32MaxTermsPerGroup) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((f32_kernel<kF32NBlock, kF32NVec, kF32NDepth, kF32NCopies, FinF32>), dim3(grid),
-                     dim3(kF32NBlock), 0, s, x, (long long)n, M, FinF32{out});
-  return hipGetLastError();
+  return launch_narrow(NarrowSumF32{x}, n, out, M, s, grid);
 }
 
 hipError_t launch_dot_f32(const float *x, const float *y, int64_t n, float *out, GlobalAcc *M, hipStream_t s,
-                          int grid, bool small, int precombine) {
+                          int grid, bool small, int) {
+  if (grid < 1) grid = 1;
+  if (small) {
+    hipLaunchKernelGGL((small_kernel<256, SrcDotF32, FinF32>), dim3(grid), dim3(256), 0, s, SrcDotF32{x, y},
+                       (long long)n, M, FinF32{out});
+    return hipGetLastError();
+  }
   if (((reinterpret_cast<uintptr_t>(x) ^ reinterpret_cast<uintptr_t>(y)) & 15) == 0)
-    return launch_op<kDotF32Block, kDotF32Vec>(SrcDotF32<true>{x, y}, n, FinF32{out}, M, s, grid, small, precombine);
-  return launch_op<kDotF32Block, kDotF32Vec>(SrcDotF32<false>{x, y}, n, FinF32{out}, M, s, grid, small, precombine);
+    return launch_narrow(NarrowDotF32<true>{x, y}, n, out, M, s, grid);
+  return launch_narrow(NarrowDotF32<false>{x, y}, n, out, M, s, grid);
 }
 
 hipError_t launch_acc_add(const double *x, int64_t n, GlobalAcc *acc, GlobalAcc *M, hipStream_t s, int grid,

@@ -215,6 +215,43 @@ def test_f32_large_accumulator(ex):
         ex.exsum_set_config(base)
 
 
+def test_dot_f32_large_accumulator(ex):
+    """The binary32 dot product's large path: products split into two 24-bit
+    halves 24 exponents apart.  Cases: every product in one chunk, products
+    of the largest significands many times over, subnormal operands, zeros of
+    both signs, operands at the exponent extremes, y misaligned against x,
+    grids with empty or tiny ranges."""
+    rng = np.random.default_rng(45)
+    n = 1_000_003
+    one = ((1.0 + rng.random(n)).astype(np.float32), (1.0 + rng.random(n)).astype(np.float32))
+    big_m = np.array([0x3FFFFFFF], dtype=np.uint32).view(np.float32)[0]
+    heavy = (np.full((1 << 25) + 5, big_m), np.full((1 << 25) + 5, -big_m))
+    sub = rng.integers(1, 1 << 23, size=n, dtype=np.uint64).astype(np.uint32).view(np.float32)
+    subnormal = (sub, f32_bits(n, 46))
+    zx = rng.standard_normal(n).astype(np.float32)
+    zx[rng.random(n) < 0.4] = 0.0
+    zx[rng.random(n) < 0.1] = -0.0
+    zeros = (zx, rng.standard_normal(n).astype(np.float32))
+    ext_e = rng.choice(np.array([1, 2, 253, 254], dtype=np.uint32), size=(2, n))
+    ext_b = (ext_e << np.uint32(23)) | rng.integers(0, 1 << 23, size=(2, n), dtype=np.uint64).astype(np.uint32)
+    ext_b |= rng.integers(0, 2, size=(2, n), dtype=np.uint64).astype(np.uint32) << np.uint32(31)
+    extremes = (ext_b[0].view(np.float32), ext_b[1].view(np.float32))
+    base = ex.exsum_get_config()
+    try:
+        for x, y in (one, heavy, subnormal, zeros, extremes):
+            want = int(oracle.dot_f32(x, y))
+            xt, yt = dev(x), dev(y)
+            for grid in (0, 1, 3, 1000):
+                with_config(ex, small_max=0, large_grid=grid)
+                assert u32(ex.exsum_dot_f32(xt, yt)) == want, (x.size, grid)
+            with_config(ex, small_max=0, large_grid=0)
+            yb = dev(np.concatenate([[np.float32(0)], y]))
+            assert u32(ex.exsum_dot_f32(xt, yb[1:])) == want, "y misaligned"
+            ex.exsum_set_config(base)
+    finally:
+        ex.exsum_set_config(base)
+
+
 def test_accumulator_add_merge_round(ex):
     parts = [W.uniform_exponent(n, seed=20 + n) for n in (0, 1, 1000, 4097, 300001)]
     parts.append(W.adversarial(4000, seed=21))
