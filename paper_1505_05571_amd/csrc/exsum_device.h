@@ -217,17 +217,30 @@ __device__ __forceinline__ unsigned int readlane_u32(unsigned int v, int lane) {
   return (unsigned int)__builtin_amdgcn_readlane((int)v, lane);
 }
 
+// Cross-lane moves on the DPP path of the vector unit (a few cycles, where a
+// general shuffle goes through the LDS crossbar).  DPP controls (GFX9):
+// row_shr:k = 0x110 + k, wave_shr:1 = 0x138, row_bcast:15 = 0x142,
+// row_bcast:31 = 0x143.  Lanes without a source keep `old`.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ unsigned int dpp_u32(unsigned int old, unsigned int v) {
+  return (unsigned int)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROW_MASK, 0xF, false);
+}
+// Lane i receives v from lane i - 1; lane 0 receives `first`.
+__device__ __forceinline__ unsigned long long shr1_u64(unsigned long long v, unsigned long long first) {
+  const unsigned int lo = dpp_u32<0x138>((unsigned int)first, (unsigned int)v);
+  const unsigned int hi = dpp_u32<0x138>((unsigned int)(first >> 32), (unsigned int)(v >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+
 // One parallel carry step on the 67 chunks held as digit i = A (lane i) for
 // i < 64 and digit 64 + j = B (lane j) for j < 3:  c_i <- low32(c_i) +
 // (c_{i-1} >> 32); the top digit (66) keeps its high part.  Value unchanged.
 __device__ __forceinline__ void carry_step_regs(long long &A, long long &B, int lane) {
   const long long hiA = A >> 32, hiB = B >> 32;
   const long long loA = A & 0xFFFFFFFFll, loB = B & 0xFFFFFFFFll;
-  long long cA = (long long)__shfl_up((unsigned long long)hiA, 1, 64);
-  if (lane == 0) cA = 0;
+  const long long cA = (long long)shr1_u64((unsigned long long)hiA, 0ull);
   const long long hiA63 = (long long)readlane_u64((unsigned long long)hiA, 63);
-  long long cB = (long long)__shfl_up((unsigned long long)hiB, 1, 64);
-  if (lane == 0) cB = hiA63;
+  const long long cB = (long long)shr1_u64((unsigned long long)hiB, (unsigned long long)hiA63);
   A = loA + cA;
   if (lane < 2) B = loB + cB;
   else if (lane == 2) B = B + cB;
@@ -241,7 +254,7 @@ __device__ __forceinline__ void carry_step_regs(long long &A, long long &B, int 
 // A digit in [1, 2^32 - 2] absorbs any carry; 0 passes a -1 on; 2^32 - 1
 // passes a +1 on; -1 sends -1 unless it receives +1; 2^32 sends +1 unless
 // it receives -1.  An inclusive scan of map compositions across the lanes
-// (six shuffles) gives every digit its carry in.
+// (six DPP steps) gives every digit its carry in.
 __device__ __forceinline__ unsigned int carry_map(long long d) {
   if (d == -1) return 0u | (0u << 2) | (1u << 4);
   if (d == 0) return 0u | (1u << 2) | (1u << 4);
@@ -277,15 +290,20 @@ __device__ inline WaveMag wave_magnitude(const long long *c, int lane) {
   long long B = (lane < 3) ? c[64 + lane] : 0;
   carry_step_regs(A, B, lane);
   carry_step_regs(A, B, lane);
-  // carries in of digits 0..63 by a scan of carry maps
+  // carries in of digits 0..63 by an inclusive scan of carry maps: within
+  // each row of 16 lanes (row_shr 1, 2, 4, 8), then row 0's total into row
+  // 1 and row 2's into row 3 (row_bcast:15), then rows 0-1's into rows 2-3
+  // (row_bcast:31); lanes without a source compose with the identity map
+  constexpr unsigned int kId = 0u | (1u << 2) | (2u << 4);   // c -> c
   unsigned int F = carry_map(A);
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const unsigned int below = (unsigned int)__shfl_up((int)F, off, 64);
-    if (lane >= off) F = carry_compose(F, below);
-  }
-  const unsigned int Fprev = (unsigned int)__shfl_up((int)F, 1, 64);
-  const int cin = (lane == 0) ? 0 : carry_apply(Fprev, 0);
+  F = carry_compose(F, dpp_u32<0x111>(kId, F));
+  F = carry_compose(F, dpp_u32<0x112>(kId, F));
+  F = carry_compose(F, dpp_u32<0x114>(kId, F));
+  F = carry_compose(F, dpp_u32<0x118>(kId, F));
+  F = carry_compose(F, dpp_u32<0x142, 0xA>(kId, F));
+  F = carry_compose(F, dpp_u32<0x143, 0xC>(kId, F));
+  const unsigned int Fprev = dpp_u32<0x138>(kId, F);          // lane 0: the identity, carry in 0
+  const int cin = carry_apply(Fprev, 0);
   unsigned int dA = (unsigned int)(A + cin);
   // digits 64, 65 and the top take the remaining carries in order
   long long cy = carry_apply((unsigned int)__builtin_amdgcn_readlane((int)F, 63), 0);
