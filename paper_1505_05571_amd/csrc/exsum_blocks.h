@@ -417,14 +417,9 @@ __device__ __forceinline__ unsigned long long f32_to_f64_bits(unsigned int b) {
   const int p = 31 - __clz(m);                       // leading bit of a denormal, 0..22
   return s | ((unsigned long long)(p + 874) << 52) | (((unsigned long long)m << (52 - p)) & ((1ull << 52) - 1));
 }
-// A normal binary32 value (exponent field 1..254) as binary64 bits: the
-// exponent is rebiased by an add and the fraction moves up 29 bits.
-__device__ __forceinline__ unsigned long long f32_normal_to_f64_bits(unsigned int b) {
-  return ((unsigned long long)(b & 0x80000000u) << 32) | ((((unsigned long long)(b & 0x7FFFFFFFu)) << 29) + (896ull << 52));
-}
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 // binary32 terms for the small-only kernel (scalar loads; the large path of
-// binary32 sums is the 512-chunk binary32 accumulator below).
+// binary32 sums is the narrow accumulator below).
 struct SrcF32 {
   const float *x;
   typedef unsigned int Raw;
