@@ -1,14 +1,15 @@
 // kernels_sum.hip -- one exact sum per launch: the large-accumulator kernel,
-// the small-only kernel, and the inexact comparator (gfx950, wave64).
+// its narrow form for binary32 inputs, the small-only kernel, the streaming
+// accumulator's kernels and the inexact comparator (gfx950, wave64).
 //
 // Large kernel: workgroup b owns terms [n*b/G, n*(b+1)/G) and a private large
 // superaccumulator in LDS; it transfers every used chunk into its small
-// superaccumulator and publishes that as a row; rows are added with integer
-// arithmetic in two levels (groups of workgroups, then groups) and the last
-// finisher rounds once (Discussion: split the array, sum the parts exactly,
-// add the small superaccumulators, round the total).  One workgroup per
-// compute unit is the intended grid: each holds the whole LDS budget it needs
-// and is never starved by a younger workgroup on the same unit.
+// superaccumulator, adds that into one shared accumulator with 64-bit device
+// atomics, and the workgroup that completes the grid applies the finisher
+// once (Discussion: split the array, sum the parts exactly, add the small
+// superaccumulators, round the total).  One workgroup per compute unit is the
+// intended grid: each holds the whole LDS budget it needs and is never
+// starved by a younger workgroup on the same unit.
 #include "exsum_blocks.h"
 #include "exsum_internal.h"
 
