@@ -198,12 +198,13 @@ def test_f32_large_accumulator(ex):
     sub_b |= (rng.integers(0, 2, size=sub_b.size, dtype=np.uint64).astype(np.uint32) << np.uint32(31))
     subnormal_and_e1 = sub_b.view(np.float32)                               # exponent field 0 or 1
     mixed = f32_bits(100003, 43)
+    few = f32_bits(5, 44)                                                   # most ranges empty at grid 1000
     with_zeros = rng.standard_normal(1_000_003).astype(np.float32)
     with_zeros[rng.random(with_zeros.size) < 0.5] = 0.0
     with_zeros[rng.random(with_zeros.size) < 0.1] = -0.0
     base = ex.exsum_get_config()
     try:
-        for x in (one_chunk, heavy, subnormal_and_e1, mixed, with_zeros):
+        for x in (one_chunk, heavy, subnormal_and_e1, mixed, with_zeros, few):
             want = int(oracle.sum_f32(x))
             xt = dev(x)
             for pre in (base.precombine, 0):
@@ -238,7 +239,7 @@ def test_dot_f32_large_accumulator(ex):
     extremes = (ext_b[0].view(np.float32), ext_b[1].view(np.float32))
     base = ex.exsum_get_config()
     try:
-        for x, y in (one, heavy, subnormal, zeros, extremes):
+        for x, y in (one, heavy, subnormal, zeros, extremes, (f32_bits(7, 47), f32_bits(7, 48))):
             want = int(oracle.dot_f32(x, y))
             xt, yt = dev(x), dev(y)
             for grid in (0, 1, 3, 1000):
