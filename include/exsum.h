@@ -91,7 +91,8 @@ int exsum_f64(const double *x, int64_t n, double *out, void *stream);
  * separately are added as small superaccumulators).
  *   x       : terms, device memory.
  *   offsets : nseg+1 int64 values, device memory, non-decreasing;
- *             offsets[0] need not be 0.  Not checked on the device.
+ *             offsets[0] need not be 0.  Not checked here (see
+ *             exsum_check_offsets).
  *   nseg    : number of segments, 0 <= nseg < 2^31.  An empty segment sums
  *             to +0.0.
  *   out     : nseg binary64 results, device memory.
@@ -101,6 +102,23 @@ int exsum_f64(const double *x, int64_t n, double *out, void *stream);
  */
 int exsum_segmented_f64(const double *x, const int64_t *offsets, int64_t nseg,
                         double *out, void *stream);
+
+/*
+ * exsum_check_offsets -- validate the offsets of a segmented call (a
+ * debugging aid: exsum_segmented_f64 trusts its offsets, and offsets past the
+ * end of x make it read outside x).
+ *   offsets   : nseg+1 int64 values, device memory.
+ *   nseg      : number of segments, 0 <= nseg < 2^31.
+ *   n         : the number of terms in x, or -1 to skip that bound.
+ *   first_bad : one int64, device memory; receives -1 if offsets[0] >= 0,
+ *               the offsets do not decrease and offsets[nseg] <= n (when
+ *               n >= 0), else the smallest segment index i whose bounds
+ *               break one of these (i = 0 for offsets[0] < 0, i = nseg-1 for
+ *               offsets[nseg] > n).
+ * Asynchronous on `stream`; allocates nothing, so it may be captured in a
+ * HIP graph.  Returns EXSUM_EINVAL for nseg out of range or NULL pointers.
+ */
+int exsum_check_offsets(const int64_t *offsets, int64_t nseg, int64_t n, int64_t *first_bad, void *stream);
 
 /*
  * exsum_inexact_f64 -- out[0] = an ordinary (rounded at every addition)

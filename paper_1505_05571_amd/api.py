@@ -13,7 +13,7 @@ import threading
 
 __all__ = [
     "ExsumError", "ExsumConfig", "library_path", "load_library",
-    "exsum_f64", "exsum_segmented_f64", "exsum_inexact_f64", "exsum_f64_cfg",
+    "exsum_f64", "exsum_segmented_f64", "exsum_check_offsets", "exsum_inexact_f64", "exsum_f64_cfg",
     "exsum_get_config", "exsum_set_config", "exsum_release", "exsum_status_string",
     "exsum_autotune", "exsum_load_tuning",
     "ServerConfig", "Server", "exsum_server_default_config", "exsum_server_plan", "exsum_serial_replay",
@@ -38,7 +38,7 @@ EXPORTED_SYMBOLS = [
     "exsum_server_replay", "exsum_serial_replay", "exsum_server_plan",
     "exsum_sqnorm_f64", "exsum_dot_f64", "exsum_mean_f64", "exsum_f32",
     "exsum_acc_zero", "exsum_acc_add_f64", "exsum_acc_merge", "exsum_acc_round_f64",
-    "exsum_autotune", "exsum_load_tuning", "exsum_dot_f32",
+    "exsum_autotune", "exsum_load_tuning", "exsum_dot_f32", "exsum_check_offsets",
 ]
 
 EXSUM_ACC_BYTES = 576
@@ -140,6 +140,8 @@ def load_library():
         lib.exsum_f32.argtypes = [P, I64, P, P]
         lib.exsum_dot_f32.argtypes = [P, P, I64, P, P]
         lib.exsum_dot_f32.restype = I32
+        lib.exsum_check_offsets.argtypes = [P, I64, I64, P, P]
+        lib.exsum_check_offsets.restype = I32
         lib.exsum_acc_zero.argtypes = [P, P]
         lib.exsum_acc_add_f64.argtypes = [P, P, I64, P]
         lib.exsum_acc_merge.argtypes = [P, P, P]
@@ -228,6 +230,21 @@ def exsum_inexact_f64(x, out=None, stream=None):
     _check(load_library().exsum_inexact_f64(_ptr(x), x.numel(), _ptr(out), _stream_handle(stream)),
            "exsum_inexact_f64")
     return out
+
+
+def exsum_check_offsets(offsets, n=None, stream=None):
+    """Validate segment offsets on the device: a 1-element int64 device tensor
+    holding -1 when offsets[0] >= 0, the offsets do not decrease and (if n is
+    given) offsets[-1] <= n, else the first segment index that breaks them."""
+    import torch
+    if not isinstance(offsets, torch.Tensor) or not offsets.is_cuda or offsets.dtype != torch.int64:
+        raise TypeError("offsets must be an int64 device tensor")
+    offsets = offsets.contiguous()
+    nseg = max(offsets.numel() - 1, 0)
+    first_bad = torch.empty(1, dtype=torch.int64, device=offsets.device)
+    _check(load_library().exsum_check_offsets(_ptr(offsets), nseg, -1 if n is None else int(n), _ptr(first_bad),
+                                               _stream_handle(stream)), "exsum_check_offsets")
+    return first_bad
 
 
 def exsum_segmented_f64(x, offsets, out=None, stream=None):

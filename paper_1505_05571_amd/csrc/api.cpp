@@ -245,6 +245,12 @@ int exsum_segmented_f64(const double *x, const int64_t *offsets, int64_t nseg, d
                                     c.precombine));
 }
 
+int exsum_check_offsets(const int64_t *offsets, int64_t nseg, int64_t n, int64_t *first_bad, void *stream) {
+  if (nseg < 0 || nseg >= (int64_t(1) << 31) || first_bad == nullptr || (nseg > 0 && offsets == nullptr))
+    return EXSUM_EINVAL;
+  return status_of(launch_check_offsets(offsets, nseg, n, first_bad, static_cast<hipStream_t>(stream)));
+}
+
 int exsum_sqnorm_f64(const double *x, int64_t n, double *out, void *stream) {
   if (n < 0 || n >= kMaxN || out == nullptr || (n > 0 && x == nullptr)) return EXSUM_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);

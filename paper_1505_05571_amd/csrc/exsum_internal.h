@@ -65,6 +65,7 @@ size_t global_acc_bytes();
 hipError_t launch_segmented(const double *x, const int64_t *offsets, int64_t nseg, double *out,
                             GlobalAcc *accs, long long *chunks, hipStream_t s, int grid, int short_grid,
                             int64_t small_max, int precombine);
+hipError_t launch_check_offsets(const int64_t *offsets, int64_t nseg, int64_t n, int64_t *first_bad, hipStream_t s);
 int seg_short_block();
 
 // One piece of a served request (host and device layout).  `expected` is the

@@ -361,6 +361,40 @@ hipError_t launch_segmented(const double *x, const int64_t *offsets, int64_t nse
   return hipGetLastError();
 }
 
+namespace {
+// Offset validation (a debugging aid; the summing kernels trust the offsets).
+__global__ __launch_bounds__(64) void check_init_kernel(unsigned long long *first_bad) {
+  if (threadIdx.x == 0) first_bad[0] = ~0ull;
+}
+// Segment i is invalid when offsets[i] > offsets[i+1], when i = 0 and
+// offsets[0] < 0, or when i = nseg-1 and offsets[nseg] > n (n >= 0).  The
+// smallest such i is kept with an unsigned minimum, so "none" stays all ones
+// (-1 as int64).
+__global__ __launch_bounds__(256) void check_offsets_kernel(const long long *__restrict__ offsets, long long nseg,
+                                                            long long n, unsigned long long *first_bad) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nseg; i += stride) {
+    const long long a = offsets[i], b = offsets[i + 1];
+    bool bad = a > b;
+    if (i == 0 && a < 0) bad = true;
+    if (i == nseg - 1 && n >= 0 && b > n) bad = true;
+    if (bad) atomicMin(first_bad, (unsigned long long)i);
+  }
+}
+}  // namespace
+
+hipError_t launch_check_offsets(const int64_t *offsets, int64_t nseg, int64_t n, int64_t *first_bad, hipStream_t s) {
+  unsigned long long *fb = reinterpret_cast<unsigned long long *>(first_bad);
+  hipLaunchKernelGGL(check_init_kernel, dim3(1), dim3(64), 0, s, fb);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || nseg == 0) return e;
+  long long blocks = (nseg + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(check_offsets_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (const long long *)offsets,
+                     (long long)nseg, (long long)n, fb);
+  return hipGetLastError();
+}
+
 int seg_short_block() { return kShortBlock; }
 
 size_t global_acc_bytes() { return sizeof(GlobalAcc); }

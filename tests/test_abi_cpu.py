@@ -204,6 +204,10 @@ def test_further_reductions_host_checks(lib):
     assert lib.exsum_f32(None, 3, P(8), None) == 1
     assert lib.exsum_dot_f32(P(8), None, 3, P(8), None) == 1
     assert lib.exsum_dot_f32(P(8), P(8), -1, P(8), None) == 1
+    assert lib.exsum_check_offsets(P(8), -1, -1, P(8), None) == 1
+    assert lib.exsum_check_offsets(None, 3, -1, P(8), None) == 1
+    assert lib.exsum_check_offsets(P(8), 3, -1, None, None) == 1
+    assert lib.exsum_check_offsets(P(8), 1 << 31, -1, P(8), None) == 1
     # the accumulator state must be 64-byte aligned device memory
     assert lib.exsum_acc_zero(None, None) == 1
     assert lib.exsum_acc_zero(P(64 + 8), None) == 1

@@ -17,6 +17,8 @@ def ex():
         pytest.skip("no HIP device")
     import paper_1505_05571_amd as ex
     ex.load_library()
+    if not DEFAULT:
+        DEFAULT.append(ex.exsum_get_config())
     yield ex
     ex.exsum_set_config(DEFAULT[0])
 
@@ -167,3 +169,26 @@ def test_many_segments_count_partition(ex):
     # a slice below the threshold takes the weight partition
     sub = off[:200001] - off[0]
     assert np.array_equal(seg_bits(ex, dev(x[:int(sub[-1])]), dev(sub)), want[:200000])
+
+
+def test_check_offsets(ex):
+    """The offset validator: -1 for valid offsets, else the first segment
+    whose bounds break them (a decrease, a negative start, an end past n)."""
+    cases = [
+        ([0, 3, 3, 10], 10, -1),
+        ([5, 7, 9], None, -1),                 # offsets[0] need not be 0
+        ([0], 0, -1),                          # no segments
+        ([0, 4, 2, 6, 1], 6, 1),               # first decrease at segment 1
+        ([-1, 2, 3], None, 0),                 # negative start
+        ([0, 2, 11], 10, 1),                   # end past n
+        ([0, 2, 11], None, -1),                # ... not checked without n
+    ]
+    for off, n, want in cases:
+        t = torch.tensor(off, dtype=torch.int64, device="cuda:0")
+        got = ex.exsum_check_offsets(t, n)
+        torch.cuda.synchronize()
+        assert int(got.item()) == want, (off, n)
+    big = torch.arange(0, 3 * 300001, 3, dtype=torch.int64, device="cuda:0")
+    assert int(ex.exsum_check_offsets(big, 3 * 300000).item()) == -1
+    big[200000] = 1                                                   # segment 199999 now decreases
+    assert int(ex.exsum_check_offsets(big, 3 * 300000).item()) == 199999
