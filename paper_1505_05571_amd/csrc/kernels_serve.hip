@@ -55,7 +55,8 @@ __global__ __launch_bounds__(BLOCK) void piece_kernel(const Table P, int nshort,
     for (int p = (int)blockIdx.x * NW + wave; p < nshort; p += (int)gridDim.x * NW) {
       const Piece pc = P[p];
       small_wave_zero<kPieceCopies>(acc, spec, lane);
-      small_wave_accumulate<kPieceCopies>(acc, spec, SrcF64{pc.x}, 0, pc.n, lane);
+      // a whole request (one piece) is rounded here and merged nowhere
+      small_wave_accumulate<kPieceCopies>(acc, spec, SrcF64{pc.x}, 0, pc.n, lane, pc.expected == 1u);
       GlobalAcc *g = pc.expected == 1u ? nullptr : &slots[pc.slot];
       wave_merge_and_round(acc, spec, g, pc.expected, pc.out, lane);
     }
