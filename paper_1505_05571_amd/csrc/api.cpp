@@ -199,9 +199,12 @@ int exsum_inexact_f64(const double *x, int64_t n, double *out, void *stream) {
   int dev = 0;
   int st = get_workspace(s, &w, &dev);
   if (st != EXSUM_OK) return st;
-  const int64_t want = (n + 8191) / 8192;
+  // the exact kernel's geometry: one workgroup per compute unit, fewer for
+  // inputs under about four tiles per workgroup
+  const int64_t tile_terms = int64_t(2) * inexact_block() * 4;
+  const int64_t want = (n + 4 * tile_terms - 1) / (4 * tile_terms);
   const int grid = (int)std::min<int64_t>(std::max<int64_t>(want, 1),
-                                          std::min<int64_t>(int64_t(4) * cu_count(dev), w->max_grid));
+                                          std::min<int64_t>(int64_t(cu_count(dev)), w->max_grid));
   return status_of(launch_inexact(x, n, w->partials, w->ticket, out, s, grid));
 }
 

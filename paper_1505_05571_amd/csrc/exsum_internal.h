@@ -34,6 +34,7 @@ hipError_t launch_large(const double *x, int64_t n, GlobalAcc *M, double *out, h
 bool large_variant_exists(int block, int vec, int depth, int mode);
 hipError_t launch_small(const double *x, int64_t n, GlobalAcc *M, double *out, hipStream_t s,
                         int grid);
+int inexact_block();
 hipError_t launch_inexact(const double *x, int64_t n, double *partials, unsigned int *ticket,
                           double *out, hipStream_t s, int grid);
 

@@ -111,14 +111,19 @@ __global__ __launch_bounds__(64) void acc_round_kernel(const GlobalAcc *acc, dou
   if (lane == 0) out[0] = __longlong_as_double((long long)r);
 }
 
-// Inexact comparator: ordinary binary64 additions per thread (2*VEC
-// independent accumulators), then wave, block and a fixed-order tree over the
-// per-workgroup partials in the last workgroup.
-template <int BLOCK, int VEC>
+// Inexact comparator: ordinary binary64 additions on the exact kernel's load
+// path (one workgroup per compute unit, per-wave contiguous streams, 16-byte
+// non-temporal loads, DEPTH tiles in flight, past-the-end prefetches on the
+// pad tile), 2*VEC independent accumulators per lane, then wave, block and a
+// fixed-order tree over the per-workgroup partials in the last workgroup.
+template <int BLOCK, int VEC, int DEPTH>
 __global__ __launch_bounds__(BLOCK) void inexact_kernel(const double *__restrict__ x, long long n,
                                                         double *__restrict__ partials,
                                                         unsigned int *__restrict__ ticket,
                                                         double *__restrict__ out) {
+  constexpr int NW = BLOCK / 64;
+  constexpr int TILE_W = 64 * VEC;
+  static_assert(VEC <= kMaxVec, "pad tile too small");
   __shared__ double s_red[BLOCK / 64];
   __shared__ unsigned int s_ticket;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -132,18 +137,42 @@ __global__ __launch_bounds__(BLOCK) void inexact_kernel(const double *__restrict
     const long long s0 = r0 + head;
     const long long nv = (r1 - s0) >> 1;
     if (tid == 0 && head) a[0] += x[r0];
-    if (tid == 1 && ((r1 - s0) & 1)) a[1] += x[r1 - 1];
-    const double2 *__restrict__ xv = reinterpret_cast<const double2 *>(x + s0);
-    constexpr int TILE_V = BLOCK * VEC;
-    long long base = 0;
-    for (; base + TILE_V <= nv; base += TILE_V) {
-      double2 v[VEC];
+    if (tid == 1 && s0 < r1 && ((r1 - s0) & 1)) a[1] += x[r1 - 1];
+    const ulonglong2 *__restrict__ xv = reinterpret_cast<const ulonglong2 *>(x + s0);
+    const long long q = nv / NW;
+    const long long ws = (long long)wave * q;
+    const long long we = (wave == NW - 1) ? nv : ws + q;
+    const long long ntiles = q / TILE_W;
+    ulonglong2 buf[DEPTH][VEC];
+    auto load = [&](ulonglong2(&bf)[VEC], long long t) {
+      const ulonglong2 *tp = (t < ntiles) ? xv + ws + t * TILE_W : g_pad_tile;
 #pragma unroll
-      for (int j = 0; j < VEC; j++) v[j] = xv[base + j * BLOCK + tid];
+      for (int j = 0; j < VEC; j++) bf[j] = stream_load(tp + lane + j * 64);
+      __builtin_amdgcn_sched_barrier(0);
+    };
+    auto process = [&](const ulonglong2(&bf)[VEC]) {
 #pragma unroll
-      for (int j = 0; j < VEC; j++) { a[2 * j] += v[j].x; a[2 * j + 1] += v[j].y; }
+      for (int j = 0; j < VEC; j++) {
+        a[2 * j] += __longlong_as_double((long long)bf[j].x);
+        a[2 * j + 1] += __longlong_as_double((long long)bf[j].y);
+      }
+    };
+    if (ntiles > 0) {
+#pragma unroll
+      for (int d = 0; d < DEPTH; d++) load(buf[d], d);
+      for (long long t = 0; t < ntiles; t += DEPTH) {
+#pragma unroll
+        for (int d = 0; d < DEPTH; d++) {
+          if (d == 0 || t + d < ntiles) process(buf[d]);
+          load(buf[d], t + d + DEPTH);
+        }
+      }
     }
-    for (long long i = base + tid; i < nv; i += BLOCK) { a[0] += xv[i].x; a[1] += xv[i].y; }
+    for (long long p = ws + ntiles * TILE_W + lane; p < we; p += 64) {
+      const ulonglong2 v = xv[p];
+      a[0] += __longlong_as_double((long long)v.x);
+      a[1] += __longlong_as_double((long long)v.y);
+    }
   }
   double s = 0.0;
 #pragma unroll
@@ -155,13 +184,15 @@ __global__ __launch_bounds__(BLOCK) void inexact_kernel(const double *__restrict
   if (tid == 0) {
     double t = 0.0;
     for (int w = 0; w < BLOCK / 64; w++) t += s_red[w];
-    partials[blockIdx.x] = t;
-    __threadfence();
-    s_ticket = atomicAdd(ticket, 1u);
+    // a device-scope store, completed before the ticket (as in the exact
+    // merge): no device-wide cache flush
+    __hip_atomic_store((unsigned long long *)&partials[blockIdx.x], (unsigned long long)__double_as_longlong(t),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    wait_memory();
+    s_ticket = ticket_add(ticket);
   }
   __syncthreads();
   if (s_ticket != gridDim.x - 1) return;
-  __threadfence();
   double t = 0.0;
   for (long long i = tid; i < G; i += BLOCK) {
     t += __longlong_as_double((long long)__hip_atomic_load((unsigned long long *)&partials[i], __ATOMIC_RELAXED,
@@ -183,6 +214,7 @@ __global__ __launch_bounds__(BLOCK) void inexact_kernel(const double *__restrict
 }  // namespace
 
 constexpr int kOpBlock = 1024;
+constexpr int kInexactBlock = 1024;
 
 // Built variants (block, vec, depth, mode).  Count mode needs
 // 2*block*vec < 4096 (the count bound per tile); carry mode does not.
@@ -326,11 +358,13 @@ hipError_t launch_acc_round(const GlobalAcc *acc, double *out, hipStream_t s) {
 
 int op_block() { return kOpBlock; }
 
+int inexact_block() { return kInexactBlock; }
+
 hipError_t launch_inexact(const double *x, int64_t n, double *partials, unsigned int *ticket, double *out,
                           hipStream_t s, int grid) {
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL((inexact_kernel<256, 4>), dim3(grid), dim3(256), 0, s, x, (long long)n, partials,
-                     ticket, out);
+  hipLaunchKernelGGL((inexact_kernel<kInexactBlock, 4, 2>), dim3(grid), dim3(kInexactBlock), 0, s, x, (long long)n,
+                     partials, ticket, out);
   return hipGetLastError();
 }
 
