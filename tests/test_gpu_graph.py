@@ -66,3 +66,41 @@ def test_capture_and_replay(ex):
         assert got[2] == int(oracle.mean_f64(xv)), rep
         assert got[3] == int(oracle.sum_f64(y)), rep
         assert np.array_equal(bits(outs), want_seg), rep
+
+
+def test_capture_binary32(ex):
+    """The binary32 sum and dot product (the narrow kernel) captured and
+    replayed, with the input changed and the outputs poisoned between
+    replays."""
+    rng = np.random.default_rng(35)
+
+    def draws(n, kmax):
+        b = ((rng.integers(0, 2, size=n, dtype=np.uint32) << np.uint32(31))
+             | (rng.integers(127 - kmax, 127 + kmax + 1, size=n, dtype=np.uint32) << np.uint32(23))
+             | rng.integers(0, 1 << 23, size=n, dtype=np.uint32))
+        return b.view(np.float32)
+
+    n = 3_000_017
+    x1, x2, y = draws(n, 60), draws(n, 60), draws(n, 40)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        xt = torch.from_numpy(x1).to("cuda:0")
+        yt = torch.from_numpy(y).to("cuda:0")
+        out = torch.empty(2, dtype=torch.float32, device="cuda:0")
+        ex.exsum_f32(xt, out=out[0:1], stream=s)              # allocates this stream's workspace
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        ex.exsum_f32(xt, out=out[0:1], stream=s)
+        ex.exsum_dot_f32(xt, yt, out=out[1:2], stream=s)
+    for rep in range(4):
+        xv = x1 if rep % 2 == 0 else x2
+        xt.copy_(torch.from_numpy(xv))
+        out.fill_(float("nan"))
+        ex.exsum_f32(yt)                                      # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().view(np.uint32)
+        assert int(got[0]) == int(oracle.sum_f32(xv)), rep
+        assert int(got[1]) == int(oracle.dot_f32(xv, y)), rep
