@@ -149,7 +149,8 @@ int exsum_inexact_f64(const double *x, int64_t n, double *out, void *stream);
  *                 wavefront and added with a single LDS update, and on the
  *                 rare slow path (tiles with infinities or NaNs, leftovers)
  *                 this many lanes sharing a chunk are summed first; 0
- *                 disables both.
+ *                 disables both.  (The binary32 kernels do not use it: their
+ *                 interleaved table copies serve a shared chunk better.)
  *   small_max   : inputs with n <= small_max use the small-only kernel.
  *   small_grid  : workgroups of the small-only kernel; 0 = automatic.
  *   seg_grid    : workgroups of the segmented call's long-segment kernel;

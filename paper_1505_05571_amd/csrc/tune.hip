@@ -366,7 +366,7 @@ int autotune_body(const char *cache_path, std::string &js, std::string &err, voi
     e = hipMemcpyAsync(B.off, off.data(), sizeof(int64_t) * (nseg + 1), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return fail(status_of(e), "copying the offsets");
     if ((st = gen(n_seg, 2, 13)) != EXSUM_OK) return fail(st, "generating an input");
-    const int64_t sms[] = {4096, 8192, 16384, 32768, 65536};
+    const int64_t sms[] = {4096, 8192, 12288, 16384, 32768, 65536};
     double bt = 1e300;
     int64_t bsm = best.seg_small_max;
     std::vector<unsigned long long> ref;
