@@ -89,7 +89,8 @@ int exsum_f64(const double *x, int64_t n, double *out, void *stream);
  * wavefronts as they come free (Performance evaluations: the small method
  * wins for short sums, the large one for long sums; Discussion: parts summed
  * separately are added as small superaccumulators).
- *   x       : terms, device memory.
+ *   x       : terms, device memory; may be NULL when every segment is
+ *             empty (offsets[0] == offsets[nseg]), and then is never read.
  *   offsets : nseg+1 int64 values, device memory, non-decreasing;
  *             offsets[0] need not be 0.  Not checked here (see
  *             exsum_check_offsets).
@@ -205,6 +206,15 @@ int exsum_autotune(const char *cache_path, char *report, int64_t report_len, voi
  */
 int exsum_load_tuning(const char *cache_path);
 
+/*
+ * exsum_large_variants -- the (block, vec, depth, mode) shapes of the large
+ * kernel this library was built with: the values exsum_set_config accepts
+ * for large_block, large_vec, large_depth and large_mode.  Writes up to
+ * `cap` shapes as 4 int32 each into out (host memory; may be NULL when
+ * cap == 0) and the number built to *count.  Host only, no device work.
+ */
+int exsum_large_variants(int32_t *out, int64_t cap, int64_t *count);
+
 /* Current configuration of the calling process (defaults until set). */
 int exsum_get_config(exsum_config *cfg);
 /* Replace the configuration; EXSUM_EINVAL if a field is out of range. */
@@ -299,7 +309,12 @@ int exsum_acc_round_f64(const void *acc, double *out, void *stream);
  *
  * The server owns: its accumulator slots (max_slots x 576 bytes of device
  * memory), pinned host and device piece tables (max_inflight x max_pieces x
- * 32 bytes each) and events, all allocated by exsum_server_create.  The
+ * 32 bytes each) and events, all allocated by exsum_server_create.
+ * Admission (Discussion, on the small superaccumulators of parts: each part
+ * in flight holds one): a request cut into pieces needs a free slot and room
+ * in mem_budget; shorter requests are admitted at once and wait only for
+ * room in a step.  LDS is not a separate limit: a step's launch holds at
+ * most one workgroup per compute unit, each within the unit's LDS.  The
  * caller owns x and out and keeps them alive until the request completes.
  * A server is used from one host thread at a time.
  * ------------------------------------------------------------------------ */
@@ -313,6 +328,14 @@ typedef struct {
     int32_t max_pieces;    /* most pieces in one step, 1 .. 2^20 (default 16384) */
     int32_t max_inflight;  /* steps queued on the stream at once, 1 .. 64 (default 2) */
     int32_t precombine;    /* as in exsum_config (default 16) */
+    int64_t mem_budget;    /* bytes of device memory that admitted requests may hold
+                              at once: 576 per accumulator slot of a request cut
+                              into pieces, plus 32 per piece descriptor of the
+                              steps queued on the stream.  A long request is
+                              admitted only when its slot and one piece fit beside
+                              what is already held, and a step's pieces are capped
+                              by what is left.  0 = no limit beyond max_slots and
+                              max_pieces (default); else >= 608 */
 } exsum_server_config;
 
 typedef struct exsum_server exsum_server;

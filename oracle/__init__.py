@@ -63,6 +63,8 @@ def _load():
         lib.exo_sum_f32.restype = ctypes.c_uint32
         lib.exo_dot_f32.argtypes = [P, P, I64]
         lib.exo_dot_f32.restype = ctypes.c_uint32
+        lib.exo_ranges_by_prefix_f64.argtypes = [P, I64, P, P, I64, I64, ctypes.c_int, P]
+        lib.exo_ranges_by_prefix_f64.restype = ctypes.c_int
         lib.exo_sum_f64_mt.argtypes = [P, I64, ctypes.c_int]
         lib.exo_sum_f64_mt.restype = ctypes.c_uint64
         _lib = lib
@@ -109,6 +111,23 @@ def sum_ranges_f64(x, starts, lens) -> np.ndarray:
     out = np.zeros(st.size, dtype=np.uint64)
     if st.size:
         _load().exo_sum_ranges_f64(_ptr(a), _ptr(st), _ptr(ln), st.size, _ptr(out))
+    return out
+
+
+def ranges_by_prefix_f64(x, starts, lens, stride: int = 1 << 16, nthreads: int = 1) -> np.ndarray:
+    """The same bits as sum_ranges_f64, through exact prefix sums every
+    `stride` terms (a finite pool only): each range costs at most about
+    2*stride terms, so long traces of slices of one pool are checked in full."""
+    a = _f64(x)
+    st = np.ascontiguousarray(starts, dtype=np.int64)
+    ln = np.ascontiguousarray(lens, dtype=np.int64)
+    out = np.zeros(st.size, dtype=np.uint64)
+    rc = _load().exo_ranges_by_prefix_f64(_ptr(a), a.size, _ptr(st), _ptr(ln), st.size, int(stride),
+                                          int(nthreads), _ptr(out))
+    if rc == -1:
+        raise ValueError("the pool holds an infinity or NaN; prefix sums need a finite pool")
+    if rc != 0:
+        raise ValueError("a range lies outside the pool, or stride < 1")
     return out
 
 

@@ -454,3 +454,87 @@ uint64_t exo_sum_f64_mt(const double *x, int64_t n, int nthreads)
     free(tids);
     return acc_result(&total, 1, 52, 2047, 64);
 }
+
+/*
+ * Exact sums of many ranges of one finite pool through exact prefix sums, so
+ * that a long trace of requests (slices of one resident pool) can be checked
+ * in full.  Integer addition is exact and associative (Discussion: parts of a
+ * sum are summed separately and added), so with P(k) = the positive and
+ * negative wide sums of x[0 .. k*stride), the sum of x[a .. b) is
+ *     P(kb) - P(ka) + (the terms x[a .. ka*stride) and x[kb*stride .. b)),
+ * where ka = ceil(a / stride) and kb = floor(b / stride); when ka > kb the
+ * range lies inside one stride and its terms are summed directly.  Each of
+ * the two wide sums only grows with k, so both subtractions are of a smaller
+ * unsigned integer from a larger one.  Infinities and NaNs cannot be
+ * differenced: the pool must be finite.
+ * Returns 0, or -1 (writing nothing) if the pool holds an infinity or NaN,
+ * -2 for a range outside [0, n) or stride < 1.
+ */
+typedef struct {
+    wide_t pos, neg;
+} prefix_t;
+
+typedef struct {
+    const double *x;
+    const prefix_t *cp;
+    int64_t stride;
+    const int64_t *starts, *lens;
+    int64_t lo, hi;
+    uint64_t *out;
+} ranges_job_t;
+
+static void *ranges_run(void *arg)
+{
+    ranges_job_t *j = (ranges_job_t *)arg;
+    for (int64_t r = j->lo; r < j->hi; r++) {
+        int64_t a = j->starts[r], b = a + j->lens[r];
+        int64_t ka = (a + j->stride - 1) / j->stride, kb = b / j->stride;
+        acc_t acc;
+        acc_init(&acc);
+        if (ka > kb) {
+            for (int64_t i = a; i < b; i++) acc_add_f64(&acc, j->x[i]);
+        } else {
+            wide_sub(&acc.pos, &j->cp[kb].pos, &j->cp[ka].pos);
+            wide_sub(&acc.neg, &j->cp[kb].neg, &j->cp[ka].neg);
+            for (int64_t i = a; i < ka * j->stride; i++) acc_add_f64(&acc, j->x[i]);
+            for (int64_t i = kb * j->stride; i < b; i++) acc_add_f64(&acc, j->x[i]);
+        }
+        j->out[r] = acc_result(&acc, 1, 52, 2047, 64);
+    }
+    return NULL;
+}
+
+int exo_ranges_by_prefix_f64(const double *x, int64_t n, const int64_t *starts, const int64_t *lens,
+                             int64_t nr, int64_t stride, int nthreads, uint64_t *out)
+{
+    if (stride < 1 || n < 0) return -2;
+    for (int64_t r = 0; r < nr; r++)
+        if (starts[r] < 0 || lens[r] < 0 || starts[r] > n - lens[r]) return -2;
+    int64_t K = n / stride;
+    prefix_t *cp = (prefix_t *)calloc((size_t)K + 1, sizeof(prefix_t));
+    if (!cp) return -2;
+    acc_t run;
+    acc_init(&run);
+    for (int64_t k = 1; k <= K; k++) {
+        for (int64_t i = (k - 1) * stride; i < k * stride; i++) acc_add_f64(&run, x[i]);
+        cp[k].pos = run.pos;
+        cp[k].neg = run.neg;
+    }
+    for (int64_t i = K * stride; i < n; i++) acc_add_f64(&run, x[i]);
+    if (run.pos_inf || run.neg_inf || run.nan_bits) {
+        free(cp);
+        return -1;
+    }
+    if (nthreads < 1) nthreads = 1;
+    ranges_job_t *jobs = (ranges_job_t *)calloc((size_t)nthreads, sizeof(ranges_job_t));
+    pthread_t *tids = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
+    for (int t = 0; t < nthreads; t++) {
+        jobs[t] = (ranges_job_t){x, cp, stride, starts, lens, nr * t / nthreads, nr * (t + 1) / nthreads, out};
+        pthread_create(&tids[t], NULL, ranges_run, &jobs[t]);
+    }
+    for (int t = 0; t < nthreads; t++) pthread_join(tids[t], NULL);
+    free(jobs);
+    free(tids);
+    free(cp);
+    return 0;
+}

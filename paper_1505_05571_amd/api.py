@@ -15,7 +15,7 @@ __all__ = [
     "ExsumError", "ExsumConfig", "library_path", "load_library",
     "exsum_f64", "exsum_segmented_f64", "exsum_check_offsets", "exsum_inexact_f64", "exsum_f64_cfg",
     "exsum_get_config", "exsum_set_config", "exsum_release", "exsum_status_string",
-    "exsum_autotune", "exsum_load_tuning",
+    "exsum_autotune", "exsum_load_tuning", "exsum_large_variants",
     "ServerConfig", "Server", "exsum_server_default_config", "exsum_server_plan", "exsum_serial_replay",
     "exsum_sqnorm_f64", "exsum_dot_f64", "exsum_mean_f64", "exsum_f32", "exsum_dot_f32", "Accumulator",
     "EXSUM_ACC_BYTES",
@@ -39,6 +39,7 @@ EXPORTED_SYMBOLS = [
     "exsum_sqnorm_f64", "exsum_dot_f64", "exsum_mean_f64", "exsum_f32",
     "exsum_acc_zero", "exsum_acc_add_f64", "exsum_acc_merge", "exsum_acc_round_f64",
     "exsum_autotune", "exsum_load_tuning", "exsum_dot_f32", "exsum_check_offsets",
+    "exsum_large_variants",
 ]
 
 EXSUM_ACC_BYTES = 576
@@ -77,6 +78,7 @@ class ServerConfig(ctypes.Structure):
         ("max_pieces", ctypes.c_int32),
         ("max_inflight", ctypes.c_int32),
         ("precombine", ctypes.c_int32),
+        ("mem_budget", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -148,6 +150,8 @@ def load_library():
         lib.exsum_acc_round_f64.argtypes = [P, P, P]
         lib.exsum_autotune.argtypes = [ctypes.c_char_p, ctypes.c_char_p, I64, P]
         lib.exsum_autotune.restype = I32
+        lib.exsum_large_variants.argtypes = [P, I64, ctypes.POINTER(I64)]
+        lib.exsum_large_variants.restype = I32
         lib.exsum_load_tuning.argtypes = [ctypes.c_char_p]
         lib.exsum_load_tuning.restype = I32
         for name in ("exsum_sqnorm_f64", "exsum_dot_f64", "exsum_mean_f64", "exsum_f32", "exsum_acc_zero",
@@ -247,8 +251,15 @@ def exsum_check_offsets(offsets, n=None, stream=None):
     return first_bad
 
 
-def exsum_segmented_f64(x, offsets, out=None, stream=None):
-    """Exact sum of each segment x[offsets[i]:offsets[i+1]] (offsets: int64 device tensor)."""
+def exsum_segmented_f64(x, offsets, out=None, stream=None, check=True):
+    """Exact sum of each segment x[offsets[i]:offsets[i+1]] (offsets: int64 device tensor).
+
+    With ``check`` (the default) the offsets are first validated on the device
+    against x's length (exsum_check_offsets) and a bad one raises ValueError
+    before the sums run: the library itself trusts its offsets, and offsets
+    past the end of x would read outside it.  The check waits for the stream;
+    pass ``check=False`` for offsets known to be good, in timed loops and under
+    HIP graph capture."""
     import torch
     x = _dev_f64(x)
     if not isinstance(offsets, torch.Tensor) or not offsets.is_cuda or offsets.dtype != torch.int64:
@@ -260,6 +271,10 @@ def exsum_segmented_f64(x, offsets, out=None, stream=None):
     out = _dev_f64(out, "out")
     if out.numel() < nseg:
         raise ValueError("out is too small")
+    if check and nseg > 0:
+        bad = int(exsum_check_offsets(offsets, n=x.numel(), stream=stream).cpu()[0])
+        if bad >= 0:
+            raise ValueError("offsets of segment %d are out of order or outside x (%d terms)" % (bad, x.numel()))
     _check(load_library().exsum_segmented_f64(_ptr(x), _ptr(offsets), nseg, _ptr(out),
                                                _stream_handle(stream)), "exsum_segmented_f64")
     return out
@@ -369,6 +384,16 @@ class Accumulator:
         _check(load_library().exsum_acc_round_f64(self._h(), _ptr(out), _stream_handle(self._stream)),
                "exsum_acc_round_f64")
         return out
+
+
+def exsum_large_variants():
+    """The large kernel's built (block, vec, depth, mode) shapes, as tuples."""
+    lib = load_library()
+    n = ctypes.c_int64(0)
+    _check(lib.exsum_large_variants(None, 0, ctypes.byref(n)), "exsum_large_variants")
+    buf = (ctypes.c_int32 * (4 * n.value))()
+    _check(lib.exsum_large_variants(buf, n.value, ctypes.byref(n)), "exsum_large_variants")
+    return [tuple(buf[4 * k:4 * k + 4]) for k in range(n.value)]
 
 
 def exsum_get_config() -> ExsumConfig:

@@ -211,7 +211,8 @@ int exsum_inexact_f64(const double *x, int64_t n, double *out, void *stream) {
 int exsum_segmented_f64(const double *x, const int64_t *offsets, int64_t nseg, double *out, void *stream) {
   if (nseg < 0 || nseg >= (int64_t(1) << 31)) return EXSUM_EINVAL;
   if (nseg == 0) return EXSUM_OK;
-  if (x == nullptr || offsets == nullptr || out == nullptr) return EXSUM_EINVAL;
+  // x may be NULL when every segment is empty (no term is read then)
+  if (offsets == nullptr || out == nullptr) return EXSUM_EINVAL;
   exsum_config c;
   {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -341,6 +342,12 @@ int exsum_acc_merge(void *dst, const void *src, void *stream) {
 int exsum_acc_round_f64(const void *acc, double *out, void *stream) {
   if (!acc_ptr_ok(acc) || out == nullptr) return EXSUM_EINVAL;
   return status_of(launch_acc_round(static_cast<const GlobalAcc *>(acc), out, static_cast<hipStream_t>(stream)));
+}
+
+int exsum_large_variants(int32_t *out, int64_t cap, int64_t *count) {
+  if (count == nullptr || cap < 0 || (cap > 0 && out == nullptr)) return EXSUM_EINVAL;
+  *count = large_variants(out, cap);
+  return EXSUM_OK;
 }
 
 int exsum_get_config(exsum_config *cfg) {

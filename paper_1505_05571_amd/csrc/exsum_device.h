@@ -392,6 +392,7 @@ __device__ inline unsigned long long round_chunks_wave(const long long *c, unsig
   const bool sticky = wave_any_below(m, rpos);
   if (rbit && (sticky || (q & 1))) q += 1;
   unsigned long long bits = ((unsigned long long)(sh - F::U) << (F::P - 1)) + q;
+  if (bits == 0) return 0;                         // a nonzero sum that rounds to zero -> +0.0
   if ((bits >> (F::P - 1)) >= F::EMAX) bits = F::EMAX << (F::P - 1);
   return (m.neg << F::SIGN) | bits;
 }

@@ -32,6 +32,9 @@ int cu_count(int dev);
 hipError_t launch_large(const double *x, int64_t n, GlobalAcc *M, double *out, hipStream_t s,
                         int block, int vec, int depth, int mode, int grid, int precombine);
 bool large_variant_exists(int block, int vec, int depth, int mode);
+// The built (block, vec, depth, mode) variants, 4 ints each, up to cap of
+// them into out (may be NULL); returns how many are built.
+int large_variants(int32_t *out, int64_t cap);
 hipError_t launch_small(const double *x, int64_t n, GlobalAcc *M, double *out, hipStream_t s,
                         int grid);
 int inexact_block();

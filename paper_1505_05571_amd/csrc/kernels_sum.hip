@@ -252,6 +252,21 @@ bool large_variant_exists(int block, int vec, int depth, int mode) {
   return false;
 }
 
+int large_variants(int32_t *out, int64_t cap) {
+  int k = 0;
+#define EXSUM_LIST(B, V, D, MD)  \
+  if (out && k < cap) {          \
+    out[4 * k + 0] = B;          \
+    out[4 * k + 1] = V;          \
+    out[4 * k + 2] = D;          \
+    out[4 * k + 3] = MD;         \
+  }                              \
+  k++;
+  EXSUM_LARGE_VARIANTS(EXSUM_LIST)
+#undef EXSUM_LIST
+  return k;
+}
+
 hipError_t launch_small(const double *x, int64_t n, GlobalAcc *M, double *out, hipStream_t s, int grid) {
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL((small_kernel<256, SrcF64, FinF64>), dim3(grid), dim3(256), 0, s, SrcF64{x}, (long long)n, M,

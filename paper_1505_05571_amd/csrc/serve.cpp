@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <chrono>
 #include <deque>
 #include <list>
@@ -29,8 +30,15 @@ exsum_server_config default_server_config() {
   c.max_pieces = 16384;
   c.max_inflight = 2;
   c.precombine = 16;
+  c.mem_budget = 0;
   return c;
 }
+
+// Device bytes a request holds while admitted: an accumulator slot if it is
+// cut into pieces, and one piece descriptor per piece of a step in flight.
+constexpr int64_t kSlotBytes = 576;
+constexpr int64_t kPieceBytes = (int64_t)sizeof(Piece);
+constexpr int64_t kNoBudget = INT64_MAX;
 
 bool server_config_ok(const exsum_server_config &c) {
   if (c.piece_terms < 1 || c.piece_terms >= kMaxTerms) return false;
@@ -40,6 +48,9 @@ bool server_config_ok(const exsum_server_config &c) {
   if (c.max_pieces < 1 || c.max_pieces > (1 << 20)) return false;
   if (c.max_inflight < 1 || c.max_inflight > 64) return false;
   if (c.precombine < 0 || c.precombine > 64) return false;
+  // a budget must hold at least one slot and one piece, or a long request
+  // could never be admitted
+  if (c.mem_budget != 0 && c.mem_budget < kSlotBytes + kPieceBytes) return false;
   return true;
 }
 
@@ -55,7 +66,7 @@ struct PlannedPiece {
 
 class Scheduler {
  public:
-  explicit Scheduler(const exsum_server_config &c) : cfg_(c) {
+  explicit Scheduler(const exsum_server_config &c) : cfg_(c), budget_(c.mem_budget ? c.mem_budget : kNoBudget) {
     free_slots_.reserve(c.max_slots);
     for (int32_t i = c.max_slots - 1; i >= 0; i--) free_slots_.push_back(i);
   }
@@ -63,19 +74,27 @@ class Scheduler {
   void submit(int64_t id, int64_t n) { pending_.push_back(Req{id, n, 0, 0, -1}); }
 
   void release_slot(int32_t slot) {
-    if (slot >= 0) free_slots_.push_back(slot);
+    if (slot >= 0) {
+      free_slots_.push_back(slot);
+      held_ -= kSlotBytes;
+    }
   }
 
   bool idle() const { return pending_.empty() && active_.empty(); }
 
   // Plan one step.  `finals` receives (id, slot) of the requests whose last
-  // piece is in this step.
-  void plan(std::vector<PlannedPiece> &out, std::vector<std::pair<int64_t, int32_t>> &finals) {
+  // piece is in this step.  `inflight_bytes`: piece descriptors of the steps
+  // still queued on the device, which count against the memory budget.
+  void plan(std::vector<PlannedPiece> &out, std::vector<std::pair<int64_t, int32_t>> &finals,
+            int64_t inflight_bytes = 0) {
     out.clear();
     finals.clear();
-    admit();
+    admit(inflight_bytes);
     int64_t budget = cfg_.step_terms;
-    const int64_t cap = cfg_.max_pieces;
+    // pieces this step may describe: max_pieces, and what the memory budget
+    // leaves after the slots held and the steps in flight
+    int64_t cap = cfg_.max_pieces;
+    if (budget_ != kNoBudget) cap = std::min(cap, std::max<int64_t>(0, (budget_ - held_ - inflight_bytes) / kPieceBytes));
     // pass 1: one piece for every active request, oldest first (a request
     // that fits in one piece is scheduled whole or not at all)
     for (auto &r : active_) {
@@ -122,16 +141,22 @@ class Scheduler {
     int32_t slot;     // accumulator slot (requests of more than one piece), else -1
   };
 
-  // Requests that fit in one piece are admitted at once; longer ones need a
-  // free accumulator slot and otherwise wait, in order.
-  void admit() {
+  // Requests that fit in one piece are admitted at once (they hold device
+  // memory only as a piece descriptor while their step is in flight, which
+  // the step's piece cap accounts for).  A longer one needs a free
+  // accumulator slot and room in the memory budget for the slot and at least
+  // one piece beside everything already held and in flight; otherwise it
+  // waits, and the ones behind it keep their order.
+  void admit(int64_t inflight_bytes) {
     for (auto it = pending_.begin(); it != pending_.end();) {
       if (it->n <= cfg_.piece_terms) {
         active_.push_back(*it);
         it = pending_.erase(it);
-      } else if (!free_slots_.empty()) {
+      } else if (!free_slots_.empty() &&
+                 (budget_ == kNoBudget || held_ + kSlotBytes + kPieceBytes + inflight_bytes <= budget_)) {
         it->slot = free_slots_.back();
         free_slots_.pop_back();
+        held_ += kSlotBytes;
         active_.push_back(*it);
         it = pending_.erase(it);
       } else {
@@ -147,6 +172,8 @@ class Scheduler {
   }
 
   exsum_server_config cfg_;
+  int64_t budget_;         // bytes of slots and in-flight piece descriptors allowed
+  int64_t held_ = 0;       // bytes of the slots held by admitted requests
   std::list<Req> pending_;
   std::list<Req> active_;
   std::vector<int32_t> free_slots_;
@@ -161,6 +188,7 @@ struct ServerImpl {
     hipEvent_t ev = nullptr;
     Piece *host = nullptr;   // pinned
     Piece *dev = nullptr;
+    int64_t npieces = 0;
     std::vector<std::pair<int64_t, int32_t>> finals;
   };
   struct ReqInfo {
@@ -179,6 +207,7 @@ struct ServerImpl {
   Piece *dev_tables = nullptr;
   std::vector<Step> ring;
   int head = 0, tail = 0, inflight = 0;
+  int64_t inflight_pieces = 0;       // pieces of the steps queued on the stream
   std::unordered_map<int64_t, ReqInfo> reqs;
   std::deque<int64_t> done;
   int64_t next_id = 0;
@@ -246,6 +275,8 @@ struct ServerImpl {
         done.push_back(f.first);
       }
       st.finals.clear();
+      inflight_pieces -= st.npieces;
+      st.npieces = 0;
       tail = (tail + 1) % (int)ring.size();
       inflight--;
     }
@@ -257,7 +288,7 @@ struct ServerImpl {
     int st = retire();
     if (st != EXSUM_OK) return st;
     if (inflight == (int)ring.size() || sched.idle()) return EXSUM_OK;
-    sched.plan(plan, finals);
+    sched.plan(plan, finals, inflight_pieces * kPieceBytes);
     if (plan.empty()) return EXSUM_OK;
     Step &s = ring[head];
     // short pieces first, then long ones
@@ -286,6 +317,8 @@ struct ServerImpl {
     if (e == hipSuccess) e = hipEventRecord(s.ev, stream);
     if (e != hipSuccess) return status_of(e);
     s.finals = finals;
+    s.npieces = n;
+    inflight_pieces += n;
     head = (head + 1) % (int)ring.size();
     inflight++;
     if (launched) *launched = n;

@@ -56,7 +56,8 @@ def test_host_side_argument_checks(lib):
     assert lib.exsum_inexact_f64(None, -5, P(8), None) == 1
     assert lib.exsum_segmented_f64(None, None, -1, None, None) == 1
     assert lib.exsum_segmented_f64(None, None, 0, None, None) == 0   # nothing to do
-    assert lib.exsum_segmented_f64(None, P(8), 3, P(8), None) == 1
+    assert lib.exsum_segmented_f64(P(8), None, 3, P(8), None) == 1   # offsets NULL
+    assert lib.exsum_segmented_f64(P(8), P(8), 3, None, None) == 1   # out NULL
     assert lib.exsum_f64_cfg(P(8), 4, P(8), None, None) == 1
 
 
@@ -76,6 +77,40 @@ def test_config_roundtrip_and_validation(lib):
             setattr(c, field, bad)
             with pytest.raises(ex.ExsumError):
                 ex.exsum_set_config(c)
+    finally:
+        ex.exsum_set_config(c0)
+
+
+def header_variant_list():
+    """The (block, vec, depth, mode) shapes the header documents as built."""
+    text = open(HEADER).read()
+    m = re.search(r"Built \(block, vec, depth, mode\):(.*?)\.\s*\n", text, flags=re.S)
+    assert m, "variant list not found in exsum.h"
+    return [tuple(int(v) for v in t.split(",")) for t in re.findall(r"\((\d+,\d+,\d+,\d)\)", m.group(1))]
+
+
+def test_built_variants_match_header_and_config_checks(lib):
+    """One table: the variants the library reports as built are the ones the
+    header documents and exactly the shapes exsum_set_config accepts; the GPU
+    parity tests run every one of them (tests/test_gpu_sum.py reads the same
+    list from the library)."""
+    built = ex.exsum_large_variants()
+    assert len(built) == len(set(built)) == 10
+    assert sorted(built) == sorted(header_variant_list())
+    c0 = ex.exsum_get_config()
+    try:
+        for block in (64, 128, 256, 512, 768, 1024):
+            for vec in range(1, 9):
+                for depth in range(1, 6):
+                    for mode in (0, 1):
+                        c = ex.exsum_get_config()
+                        c.large_block, c.large_vec, c.large_depth, c.large_mode = block, vec, depth, mode
+                        ok = True
+                        try:
+                            ex.exsum_set_config(c)
+                        except ex.ExsumError:
+                            ok = False
+                        assert ok == ((block, vec, depth, mode) in built), (block, vec, depth, mode)
     finally:
         ex.exsum_set_config(c0)
 
@@ -154,6 +189,51 @@ def test_server_plan_shares_steps_fairly(lib):
     plan = ex.exsum_server_plan([10 * cfg.step_terms + 7], cfg)
     per_step = np.bincount(plan["step"], weights=plan["len"])
     assert np.all(per_step[:-1] == cfg.step_terms) and per_step[-1] == 7
+
+
+def test_server_plan_admits_by_memory_budget(lib):
+    """With a memory budget of two slots (576 B each) plus a few piece
+    descriptors (32 B), at most two requests that are cut into pieces hold a
+    slot at once, even with many free slots; the others wait, in order, and
+    are admitted as the first complete.  Short requests are not held back,
+    and no step describes more pieces than the budget leaves."""
+    import numpy as np
+    lens = [5000] * 6 + [10] * 5
+    free = small_cfg(max_slots=64)
+    tight = small_cfg(max_slots=64, mem_budget=2 * 576 + 4 * 32)
+    p_free = ex.exsum_server_plan(lens, free)
+    p_tight = ex.exsum_server_plan(lens, tight)
+    plan_invariants(lens, tight, p_tight)
+
+    def concurrent(plan):
+        spans = {}
+        for r in np.unique(plan["req"][plan["slot"] >= 0]):
+            st = plan["step"][plan["req"] == r]
+            spans[int(r)] = (int(st.min()), int(st.max()))
+        return max(sum(1 for a, b in spans.values() if a <= s <= b) for s in range(int(plan["step"].max()) + 1)), spans
+
+    n_free, _ = concurrent(p_free)
+    n_tight, spans = concurrent(p_tight)
+    assert n_free == 6 and n_tight == 2
+    # the waiting requests start in submission order, each after one has finished
+    starts = [spans[r][0] for r in range(6)]
+    assert starts == sorted(starts) and starts[2] > min(spans[0][1], spans[1][1])
+    # the short requests do not wait behind the long ones that wait for room:
+    # all are served before the third long request is admitted
+    assert np.all(p_tight["step"][np.isin(p_tight["req"], range(6, 11))] < starts[2])
+    assert np.all(p_free["step"][np.isin(p_free["req"], range(6, 11))] == 0)
+    # pieces per step within what the budget leaves after the held slots
+    for s in np.unique(p_tight["step"]):
+        held = sum(1 for a, b in spans.values() if a <= s <= b)
+        assert (p_tight["step"] == s).sum() * 32 + held * 576 <= tight.mem_budget
+    # a budget below one slot and one piece is rejected
+    import ctypes
+    P = ctypes.c_void_p
+    h = P(0)
+    bad = small_cfg(mem_budget=600)
+    assert lib.exsum_server_create(ctypes.byref(bad), None, ctypes.byref(h)) == 1
+    with pytest.raises(ex.ExsumError):
+        ex.exsum_server_plan(lens, bad)
 
 
 def test_server_host_side_checks(lib):

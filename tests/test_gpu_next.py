@@ -317,6 +317,9 @@ def test_dot_f32(ex):
         ([t], [t], 0),                                              # half a unit, ties to even -> +0
         ([t, u], [t, u], 1),                                        # just above half a unit
         ([3.0, -3.0, u], [5.0, 5.0, u], 0),                         # 2^-200 -> +0
+        ([-t], [t], 0),                                             # -(half a unit) -> +0, not -0
+        ([-3.0, 3.0, -u], [5.0, 5.0, u], 0),                        # -2^-200 -> +0, not -0
+        ([-t, -u], [t, u], 0x80000001),                             # just below minus half a unit
         ([1.0, 2.0 ** -12, u], [1.0, 2.0 ** -12, u], 0x3F800001),   # just above a tie
         ([fmax, fmax], [2.0, -1.0], int(np.array([fmax]).view(np.uint32)[0])),
         ([fmax], [2.0], 0x7F800000),

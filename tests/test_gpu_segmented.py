@@ -192,3 +192,19 @@ def test_check_offsets(ex):
     assert int(ex.exsum_check_offsets(big, 3 * 300000).item()) == -1
     big[200000] = 1                                                   # segment 199999 now decreases
     assert int(ex.exsum_check_offsets(big, 3 * 300000).item()) == 199999
+
+
+def test_wrapper_validates_offsets_and_empty_input(ex):
+    """The binding checks offsets against x's length before the sums run
+    (the summing kernels trust them, so no bad offset ever reaches them), and
+    an empty x with only empty segments gives +0.0 for each."""
+    x = dev(W.uniform_exponent(1000, seed=4))
+    for off in ([0, 400, 300, 1000], [0, 500, 1001], [-2, 5, 9]):
+        with pytest.raises(ValueError):
+            ex.exsum_segmented_f64(x, torch.tensor(off, dtype=torch.int64, device="cuda:0"))
+    empty = torch.empty(0, dtype=torch.float64, device="cuda:0")
+    off = torch.zeros(6, dtype=torch.int64, device="cuda:0")
+    out = torch.full((5,), np.nan, dtype=torch.float64, device="cuda:0")
+    ex.exsum_segmented_f64(empty, off, out=out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().view(np.uint64), np.zeros(5, dtype=np.uint64))

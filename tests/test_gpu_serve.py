@@ -131,3 +131,29 @@ def test_replays_batched_and_serial(ex):
     lat2, mk2 = ex.exsum_serial_replay(pt, starts, lens, arrival, out2)
     assert np.array_equal(bits(out2), want)
     assert np.all(lat2 > 0) and mk2 >= arrival[-1]
+
+
+def test_replay_2000_requests_every_result_against_the_oracle(ex):
+    """A served trace of 2,000 requests (lengths log-uniform in [10, 10^6],
+    slices of one resident pool), replayed in real time through the batching
+    server at about twice the serial service rate and then serially: every
+    request's bits equal the oracle's (exact prefix sums of the pool)."""
+    n_pool = 8_000_000
+    pool = W.uniform_exponent(n_pool, seed=7)
+    rng = np.random.default_rng(7)
+    nreq = 2000
+    lens = np.rint(10.0 ** rng.uniform(1, 6, size=nreq)).astype(np.int64)
+    starts = np.floor(rng.uniform(0, 1, size=nreq) * (n_pool - lens + 1)).astype(np.int64)
+    want = oracle.ranges_by_prefix_f64(pool, starts, lens, stride=1 << 14, nthreads=8)
+    # spacing of arrivals: about half the mean serial service time
+    arrival = np.cumsum(rng.exponential(10e-6, size=nreq))
+    pt = torch.from_numpy(pool).to("cuda:0")
+    out = torch.full((nreq,), np.nan, dtype=torch.float64, device="cuda:0")
+    with ex.Server() as srv:
+        lat, mk = srv.replay(pt, starts, lens, arrival, out)
+    got = bits(out)
+    assert int((got != want).sum()) == 0
+    assert np.all(lat > 0) and mk >= arrival[-1]
+    out2 = torch.full((nreq,), np.nan, dtype=torch.float64, device="cuda:0")
+    ex.exsum_serial_replay(pt, starts, lens, arrival, out2)
+    assert np.array_equal(bits(out2), want)

@@ -46,22 +46,26 @@ def cfg_with(ex, **kw):
     return c
 
 
-LARGE_VARIANTS = [
-    dict(large_block=256, large_vec=6, large_depth=3, large_mode=0, precombine=16),
-    dict(large_block=256, large_vec=4, large_depth=3, large_mode=1, precombine=16),
-    dict(large_block=256, large_vec=2, large_depth=4, large_mode=0, precombine=0),
-    dict(large_block=1024, large_vec=4, large_depth=2, large_mode=1, precombine=0),
-    dict(large_block=512, large_vec=2, large_depth=2, large_mode=0, precombine=32),
-    dict(large_block=512, large_vec=2, large_depth=4, large_mode=1, precombine=1),
-    dict(large_block=512, large_vec=3, large_depth=2, large_mode=0, precombine=8),
-    dict(large_block=1024, large_vec=2, large_depth=2, large_mode=1, precombine=8),
-]
+# pre-combine thresholds cycled over the built variants, so that every
+# variant runs with and without the pre-combine across the test grid
+PRECOMBINES = (16, 0, 32, 1, 8)
+
+
+def large_variants(ex):
+    """Every large-kernel shape the library is built with (the library's own
+    list, which the CPU tests check against the header and the configuration
+    checks), each with a pre-combine threshold."""
+    out = []
+    for k, (b, v, d, m) in enumerate(ex.exsum_large_variants()):
+        out.append(dict(large_block=b, large_vec=v, large_depth=d, large_mode=m,
+                        precombine=PRECOMBINES[k % len(PRECOMBINES)]))
+    return out
 
 
 def all_paths(ex):
     """Small-only path and several large-path configurations (and grids)."""
     cfgs = [cfg_with(ex, small_max=10 ** 12)]
-    for v in LARGE_VARIANTS:
+    for v in large_variants(ex):
         for grid in (0, 1, 7, 300):
             cfgs.append(cfg_with(ex, small_max=0, large_grid=grid, **v))
     return cfgs

@@ -28,6 +28,15 @@ MUTANTS = {
     "overflow_threshold": ("if (E >= emax) return emax << mbits;", "if (E > emax) return emax << mbits;"),
     "sticky_ignored": ("int sticky = wide_any_below(&Q, sh - 1) || R != 0;", "int sticky = R != 0;"),
     "shift_off_by_one": ("(int)(e_eff - 1));\n}\n\n/* Same", "(int)(e_eff));\n}\n\n/* Same"),
+    # wrong NaN rules: the first NaN seen instead of the largest, the quiet bit not set
+    "nan_first_seen": ("uint64_t payload = b & 0x7FFFFFFFFFFFFFFFull;\n            if (payload > acc->nan_bits)",
+                       "uint64_t payload = b & 0x7FFFFFFFFFFFFFFFull;\n            if (!acc->nan_bits)"),
+    "nan_quiet_bit_dropped": ("if (acc->nan_bits) return acc->nan_bits | quiet;",
+                              "if (acc->nan_bits) return acc->nan_bits;"),
+    # wrong Inf rules: +Inf with -Inf gives +Inf, -Inf loses its sign
+    "inf_pair_not_nan": ("if (acc->pos_inf && acc->neg_inf) return (emax << mbits) | quiet;", ""),
+    "neg_inf_unsigned": ("if (acc->neg_inf) return sign_bit | (emax << mbits);",
+                         "if (acc->neg_inf) return emax << mbits;"),
 }
 
 
@@ -93,6 +102,22 @@ def pins_pass(lib) -> bool:
         checks.append(s(vals) == exact_round(vals))
     x = W.uniform_exponent(3000, seed=4)
     checks.append(s(x) == bits(math.fsum(x)))
+    # specials: an infinity dominates finite terms (IEEE addition), +Inf with
+    # -Inf is the quiet NaN 0x7FF8..., a NaN term gives the largest NaN
+    # pattern (sign dropped) with the quiet bit set, in any order
+    inf = math.inf
+    checks.append(s([inf, -dmax, -dmax]) == bits(inf + (-dmax) + (-dmax)))
+    checks.append(s([-dmax, 5.0, -inf]) == bits(-inf))
+    checks.append(s([-inf]) == bits(-inf) and s([inf]) == bits(inf))
+    checks.append(s([inf, 1.0, -inf]) == 0x7FF8000000000000)
+    qa, qb = 0x7FF8000000000123, 0x7FF80000000ABCDE
+    na, nb = (np.array([v], dtype=np.uint64).view(np.float64)[0] for v in (qa, qb))
+    checks.append(s([na, nb]) == qb and s([nb, 1.0, na]) == qb)
+    snan = np.array([0x7FF0000000000001], dtype=np.uint64).view(np.float64)[0]
+    checks.append(s([snan]) == bits(np.float64(snan) + np.float64(0.0)) == 0x7FF8000000000001)
+    neg_nan = np.array([0xFFF8000000000005], dtype=np.uint64).view(np.float64)[0]
+    checks.append(s([1.0, neg_nan, inf]) == 0x7FF8000000000005)
+    checks.append(s([inf, na, -inf]) == qa)
     return all(checks)
 
 

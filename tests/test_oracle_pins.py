@@ -285,6 +285,41 @@ def test_segmented_matches_per_segment():
     assert np.array_equal(oracle.sum_ranges_f64(x, starts, lens), seg)
 
 
+def test_ranges_by_prefix_match_direct_sums():
+    """Prefix-difference range sums (the served trace's full check) against
+    the direct definition: ranges inside one stride, across strides, aligned
+    to stride boundaries, empty and the whole pool, at several strides and
+    thread counts; and, on tiny pools, against exact rationals."""
+    x = W.uniform_exponent(50021, seed=9)
+    rng = np.random.default_rng(9)
+    st, ln = [], []
+    for L in [0, 1, 2, 63, 64, 65, 127, 128, 129, 1000, 4096, 4097, 30000, 50021]:
+        for a in (0, 1, 63, 64, 128, 50021 - L):
+            if 0 <= a <= 50021 - L:
+                st.append(a)
+                ln.append(L)
+    for _ in range(300):
+        L = int(rng.integers(0, 50022))
+        st.append(int(rng.integers(0, 50022 - L)))
+        ln.append(L)
+    st, ln = np.array(st, dtype=np.int64), np.array(ln, dtype=np.int64)
+    want = oracle.sum_ranges_f64(x, st, ln)
+    for stride, threads in ((64, 1), (1, 3), (4096, 4), (1 << 16, 2), (7, 1)):
+        assert np.array_equal(oracle.ranges_by_prefix_f64(x, st, ln, stride=stride, nthreads=threads), want)
+    # long cancellation: a prefix difference of huge partial sums leaves the tiny terms
+    y = np.array([1e300, 3e-300, -1e300, 5e-310, 2.0 ** 1000, -(2.0 ** 1000), 7.0, -7.0, 1e-320], dtype=np.float64)
+    rst = np.array([0, 0, 1, 2, 3, 4, 1], dtype=np.int64)
+    rln = np.array([9, 3, 8, 7, 6, 5, 2], dtype=np.int64)
+    for stride in (1, 2, 3, 4):
+        got = oracle.ranges_by_prefix_f64(y, rst, rln, stride=stride)
+        for r in range(rst.size):
+            assert int(got[r]) == exact_round(y[rst[r]:rst[r] + rln[r]]), (stride, r)
+    with pytest.raises(ValueError):
+        oracle.ranges_by_prefix_f64(np.array([1.0, math.inf]), [0], [1])
+    with pytest.raises(ValueError):
+        oracle.ranges_by_prefix_f64(x, [50000], [22])
+
+
 # ---- specials (conventions; the paper fixes only that they are side fields) -----
 
 def test_special_values():
