@@ -359,6 +359,10 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--autotune", action="store_true",
                     help="run the library's configuration tuner before the workload (untimed)")
+    ap.add_argument("--config", default="",
+                    help="launch configuration fields to set first, e.g. "
+                         "large_mode=0,large_block=256,large_vec=6,large_depth=3 or precombine=0 "
+                         "(they change speed only, never a result bit)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -370,6 +374,16 @@ def main():
         ex.load_library()
         TUNING["label"] = "autotuned"
         TUNING["config"] = ex.exsum_autotune()["config"]
+    if args.config:
+        import paper_1505_05571_amd as ex
+        ex.load_library()
+        c = ex.exsum_get_config()
+        for item in args.config.split(","):
+            k, v = item.split("=")
+            setattr(c, k.strip(), int(v))
+        ex.exsum_set_config(c)
+        TUNING["label"] = "set: " + args.config
+        TUNING["config"] = c.as_dict()
 
     if args.workload == "serve":
         return serve_bench(args)
