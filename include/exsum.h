@@ -74,6 +74,24 @@ const char *exsum_status_string(int status);
 int exsum_f64(const double *x, int64_t n, double *out, void *stream);
 
 /*
+ * exsum_f64_noalloc -- exsum_f64 without any device allocation, for callers
+ * that cannot allocate: code under HIP graph capture before any other call
+ * on its stream, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, result bits, kernels and launch configuration as
+ * exsum_f64; instead of the per-stream workspace it uses a fixed scratch
+ * buffer in the library's static device memory: one 576-byte merge
+ * accumulator per device, held until the process ends.  Every n the
+ * scratch can serve is accepted (0 <= n < 2^40, as exsum_f64; a larger n,
+ * or a NULL x with n > 0 or a NULL out, returns EXSUM_EINVAL).  The first
+ * call on a device finds the scratch's address and clears it with a kernel
+ * on `stream`; later calls launch only the summing kernel.  The scratch is
+ * shared by every call on that device and each call leaves it cleared: calls
+ * that overlap on one device (other streams, other threads) race on it and
+ * give wrong results, so order them, e.g. on one stream.
+ */
+int exsum_f64_noalloc(const double *x, int64_t n, double *out, void *stream);
+
+/*
  * exsum_segmented_f64 -- out[i] = exact sum of x[offsets[i] .. offsets[i+1])
  * for 0 <= i < nseg.
  *

@@ -13,7 +13,8 @@ import threading
 
 __all__ = [
     "ExsumError", "ExsumConfig", "library_path", "load_library",
-    "exsum_f64", "exsum_segmented_f64", "exsum_check_offsets", "exsum_inexact_f64", "exsum_f64_cfg",
+    "exsum_f64", "exsum_f64_noalloc", "exsum_segmented_f64", "exsum_check_offsets", "exsum_inexact_f64",
+    "exsum_f64_cfg",
     "exsum_get_config", "exsum_set_config", "exsum_release", "exsum_status_string",
     "exsum_autotune", "exsum_load_tuning", "exsum_large_variants",
     "ServerConfig", "Server", "exsum_server_default_config", "exsum_server_plan", "exsum_serial_replay",
@@ -39,7 +40,7 @@ EXPORTED_SYMBOLS = [
     "exsum_sqnorm_f64", "exsum_dot_f64", "exsum_mean_f64", "exsum_f32",
     "exsum_acc_zero", "exsum_acc_add_f64", "exsum_acc_merge", "exsum_acc_round_f64",
     "exsum_autotune", "exsum_load_tuning", "exsum_dot_f32", "exsum_check_offsets",
-    "exsum_large_variants",
+    "exsum_large_variants", "exsum_f64_noalloc",
 ]
 
 EXSUM_ACC_BYTES = 576
@@ -110,6 +111,8 @@ def load_library():
         lib.exsum_status_string.argtypes = [I32]
         lib.exsum_status_string.restype = ctypes.c_char_p
         lib.exsum_f64.argtypes = [P, I64, P, P]
+        lib.exsum_f64_noalloc.argtypes = [P, I64, P, P]
+        lib.exsum_f64_noalloc.restype = I32
         lib.exsum_f64.restype = I32
         lib.exsum_f64_cfg.argtypes = [P, I64, P, P, ctypes.POINTER(ExsumConfig)]
         lib.exsum_f64_cfg.restype = I32
@@ -215,6 +218,17 @@ def exsum_f64(x, out=None, stream=None):
     x = _dev_f64(x)
     out = _out1(x, out)
     _check(load_library().exsum_f64(_ptr(x), x.numel(), _ptr(out), _stream_handle(stream)), "exsum_f64")
+    return out
+
+
+def exsum_f64_noalloc(x, out, stream=None):
+    """exsum_f64 through the entry point that allocates nothing (a static
+    per-device scratch accumulator); `out` must be given, so that no
+    allocation happens here either."""
+    x = _dev_f64(x)
+    out = _dev_f64(out, "out")
+    _check(load_library().exsum_f64_noalloc(_ptr(x), x.numel(), _ptr(out), _stream_handle(stream)),
+           "exsum_f64_noalloc")
     return out
 
 

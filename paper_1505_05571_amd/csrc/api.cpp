@@ -102,18 +102,14 @@ int get_workspace(hipStream_t s, Workspace **out, int *dev_out) {
   return EXSUM_OK;
 }
 
-int run_sum(const double *x, int64_t n, double *out, hipStream_t s, const exsum_config &c) {
-  if (n < 0 || n >= kMaxN || out == nullptr || (n > 0 && x == nullptr)) return EXSUM_EINVAL;
-  if (!config_ok(c)) return EXSUM_EINVAL;
-  Workspace *w = nullptr;
-  int dev = 0;
-  int st = get_workspace(s, &w, &dev);
-  if (st != EXSUM_OK) return st;
+// Launch the single sum with merge accumulator `acc` (zeroed, left zeroed).
+hipError_t launch_sum(const double *x, int64_t n, double *out, hipStream_t s, const exsum_config &c,
+                      GlobalAcc *acc, int dev) {
   hipError_t e;
   if (n <= c.small_max) {
     int grid = c.small_grid;
     if (grid == 0) grid = (int)std::min<int64_t>(std::max<int64_t>((n + 8191) / 8192, 1), 64);
-    e = launch_small(x, n, w->acc, out, s, grid);
+    e = launch_small(x, n, acc, out, s, grid);
   } else {
     int grid = c.large_grid;
     if (grid == 0) {
@@ -122,10 +118,20 @@ int run_sum(const double *x, int64_t n, double *out, hipStream_t s, const exsum_
       const int64_t want = (n + 4 * tile_terms - 1) / (4 * tile_terms);
       grid = (int)std::min<int64_t>(std::max<int64_t>(want, 1), int64_t(cu_count(dev)));
     }
-    e = launch_large(x, n, w->acc, out, s, c.large_block, c.large_vec, c.large_depth, c.large_mode, grid,
+    e = launch_large(x, n, acc, out, s, c.large_block, c.large_vec, c.large_depth, c.large_mode, grid,
                      c.precombine);
   }
-  return status_of(e);
+  return e;
+}
+
+int run_sum(const double *x, int64_t n, double *out, hipStream_t s, const exsum_config &c) {
+  if (n < 0 || n >= kMaxN || out == nullptr || (n > 0 && x == nullptr)) return EXSUM_EINVAL;
+  if (!config_ok(c)) return EXSUM_EINVAL;
+  Workspace *w = nullptr;
+  int dev = 0;
+  int st = get_workspace(s, &w, &dev);
+  if (st != EXSUM_OK) return st;
+  return status_of(launch_sum(x, n, out, s, c, w->acc, dev));
 }
 
 // Launch shape of a sum over the small-only kernel or the large kernel's
@@ -185,6 +191,24 @@ int exsum_f64(const double *x, int64_t n, double *out, void *stream) {
     c = g_cfg;
   }
   return run_sum(x, n, out, static_cast<hipStream_t>(stream), c);
+}
+
+int exsum_f64_noalloc(const double *x, int64_t n, double *out, void *stream) {
+  if (n < 0 || n >= kMaxN || out == nullptr || (n > 0 && x == nullptr)) return EXSUM_EINVAL;
+  exsum_config c;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    c = g_cfg;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return status_of(e);
+  if (dev < 0 || dev >= kMaxDevices) return EXSUM_EINVAL;
+  GlobalAcc *acc = nullptr;
+  e = noalloc_scratch(dev, s, &acc);
+  if (e != hipSuccess) return status_of(e);
+  return status_of(launch_sum(x, n, out, s, c, acc, dev));
 }
 
 int exsum_f64_cfg(const double *x, int64_t n, double *out, void *stream, const exsum_config *cfg) {

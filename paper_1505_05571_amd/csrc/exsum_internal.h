@@ -7,6 +7,7 @@
 namespace exsum {
 
 constexpr int kMaxGrid = 8192;       // most workgroups one single-sum launch may use
+constexpr int kMaxDevices = 64;      // devices the per-device tables hold
 
 struct GlobalAcc;
 
@@ -37,6 +38,10 @@ bool large_variant_exists(int block, int vec, int depth, int mode);
 int large_variants(int32_t *out, int64_t cap);
 hipError_t launch_small(const double *x, int64_t n, GlobalAcc *M, double *out, hipStream_t s,
                         int grid);
+// The allocation-free single sum's scratch accumulator on device `dev` (the
+// current device): its device address, found and cleared (on stream s) on
+// the first call for that device.
+hipError_t noalloc_scratch(int dev, hipStream_t s, GlobalAcc **out);
 int inexact_block();
 hipError_t launch_inexact(const double *x, int64_t n, double *partials, unsigned int *ticket,
                           double *out, hipStream_t s, int grid);

@@ -10,6 +10,8 @@
 // superaccumulators, round the total).  One workgroup per compute unit is the
 // intended grid: each holds the whole LDS budget it needs and is never
 // starved by a younger workgroup on the same unit.
+#include <mutex>
+
 #include "exsum_blocks.h"
 #include "exsum_internal.h"
 
@@ -250,6 +252,42 @@ bool large_variant_exists(int block, int vec, int depth, int mode) {
   EXSUM_LARGE_VARIANTS(EXSUM_EXISTS)
 #undef EXSUM_EXISTS
   return false;
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free single sum: the one merge accumulator that
+// the small and large kernels of exsum_f64 need (67 chunks, side words and
+// ticket, 576 bytes), in static device memory, one copy per device, held
+// until the process ends.  The kernels leave it zeroed when a call
+// completes, as they leave a stream's workspace; it is also cleared once per
+// device at set-up.  Host code never passes `scratch` itself to a kernel:
+// its device address comes from hipGetSymbolAddress, per device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) GlobalAcc scratch[1];
+
+namespace {
+std::mutex g_scratch_mu;
+GlobalAcc *g_scratch_ptr[kMaxDevices] = {nullptr};
+}  // namespace
+
+hipError_t noalloc_scratch(int dev, hipStream_t s, GlobalAcc **out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    // the calling thread's current device is `dev`
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    // clear it with a fill kernel on the caller's stream (no memset node, so
+    // a first call under graph capture records only kernels)
+    hipLaunchKernelGGL(acc_zero_kernel, dim3(1), dim3(64), 0, s, static_cast<GlobalAcc *>(p));
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<GlobalAcc *>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 int large_variants(int32_t *out, int64_t cap) {
