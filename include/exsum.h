@@ -177,8 +177,18 @@ int exsum_inexact_f64(const double *x, int64_t n, double *out, void *stream);
  *   seg_small_max : segments of at most this many terms (0 .. 2^20) are
  *                   summed by one wavefront with the small accumulator
  *                   alone; longer ones by workgroups with the large one.
- *                   (The short-segment kernel always runs one workgroup
- *                   per compute unit.)
+ *   seg_mode    : 1 = one persistent launch: workgroups sum the long
+ *                 segments of their term range, then their wavefronts claim
+ *                 short segments from a device-wide cursor, longest length
+ *                 class first; 0 = two launches (long segments, then short
+ *                 ones on one workgroup per compute unit with an even split
+ *                 of their total length).
+ *   seg_block   : threads per workgroup of the persistent launch: 256, 512
+ *                 or 1024.
+ *   seg_group   : segments per unit of the persistent launch's cursor, 1..64.
+ *   seg_pad     : unused, 0.
+ *   (seg_grid also sets the persistent launch's workgroups; 0 = as many
+ *   per compute unit as fit: three of 256 threads, two of 512, one of 1024.)
  */
 typedef struct {
     int32_t large_block;
@@ -191,6 +201,10 @@ typedef struct {
     int32_t small_grid;
     int32_t seg_grid;
     int64_t seg_small_max;
+    int32_t seg_mode;
+    int32_t seg_block;
+    int32_t seg_group;
+    int32_t seg_pad;
 } exsum_config;
 
 /*

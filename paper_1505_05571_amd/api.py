@@ -64,6 +64,10 @@ class ExsumConfig(ctypes.Structure):
         ("small_grid", ctypes.c_int32),
         ("seg_grid", ctypes.c_int32),
         ("seg_small_max", ctypes.c_int64),
+        ("seg_mode", ctypes.c_int32),
+        ("seg_block", ctypes.c_int32),
+        ("seg_group", ctypes.c_int32),
+        ("seg_pad", ctypes.c_int32),
     ]
 
     def as_dict(self):

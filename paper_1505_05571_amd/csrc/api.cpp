@@ -55,6 +55,10 @@ exsum_config default_config() {
   c.small_grid = 0;
   c.seg_grid = 0;
   c.seg_small_max = 12288;
+  c.seg_mode = 0;
+  c.seg_block = 256;
+  c.seg_group = 16;
+  c.seg_pad = 0;
   return c;
 }
 
@@ -70,6 +74,9 @@ bool config_ok(const exsum_config &c) {
   if (c.small_max < 0 || c.small_grid < 0 || c.small_grid > kMaxGrid) return false;
   if (c.seg_grid < 0 || c.seg_grid > kMaxGrid) return false;
   if (c.seg_small_max < 0 || c.seg_small_max > (int64_t(1) << 20)) return false;
+  if (c.seg_mode != 0 && c.seg_mode != 1) return false;
+  if (c.seg_block != 256 && c.seg_block != 512 && c.seg_block != 1024) return false;
+  if (c.seg_group < 1 || c.seg_group > 64 || c.seg_pad != 0) return false;
   return true;
 }
 
@@ -247,26 +254,39 @@ int exsum_segmented_f64(const double *x, const int64_t *offsets, int64_t nseg, d
   int dev = 0;
   int st = get_workspace(s, &w, &dev);
   if (st != EXSUM_OK) return st;
-  int grid = c.seg_grid;
-  if (grid == 0) grid = 2 * cu_count(dev);           // two long-segment workgroups per compute unit
   GlobalAcc *accs = nullptr;
   long long *chunks = nullptr;
+  void *ctl = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_mu);
     if (w->seg_accs == nullptr) {
       void *p = nullptr;
       const size_t abytes = global_acc_bytes() * (size_t)kMaxGrid;
-      const size_t bytes = abytes + sizeof(long long) * (size_t)kMaxGrid;
+      const size_t cbytes = sizeof(long long) * (size_t)kMaxGrid;
+      const size_t bytes = abytes + cbytes + seg_ctl_bytes();
       hipError_t e = hipMalloc(&p, bytes);
       if (e != hipSuccess) return status_of(e);
       e = hipMemset(p, 0, bytes);
       if (e != hipSuccess) { (void)hipFree(p); return status_of(e); }
       w->seg_accs = reinterpret_cast<GlobalAcc *>(p);
       w->seg_chunks = reinterpret_cast<long long *>(static_cast<char *>(p) + abytes);
+      w->seg_ctl = static_cast<char *>(p) + abytes + cbytes;
     }
     accs = w->seg_accs;
     chunks = w->seg_chunks;
+    ctl = w->seg_ctl;
   }
+  if (c.seg_mode == 1) {
+    // one persistent launch, as many workgroups per compute unit as fit its
+    // LDS and registers (three of 256 threads, two of 512, one of 1024); at
+    // most kMaxGrid (one merge slot per workgroup)
+    int pgrid = c.seg_grid;
+    if (pgrid == 0) pgrid = (c.seg_block == 1024 ? 1 : (c.seg_block == 512 ? 2 : 3)) * cu_count(dev);
+    return status_of(launch_segmented_persistent(x, offsets, nseg, out, accs, ctl, s, pgrid, c.seg_block,
+                                                 c.seg_small_max, c.precombine, c.seg_group));
+  }
+  int grid = c.seg_grid;
+  if (grid == 0) grid = 2 * cu_count(dev);           // two long-segment workgroups per compute unit
   // short segments: one workgroup per compute unit
   const int short_grid = std::min(cu_count(dev), seg_short_block());
   return status_of(launch_segmented(x, offsets, nseg, out, accs, chunks, s, grid, short_grid, c.seg_small_max,

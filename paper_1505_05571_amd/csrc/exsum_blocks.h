@@ -307,7 +307,9 @@ static __device__ ulonglong2 g_pad_tile[64 * kMaxVec];
 //                      load_plain(p, k) an ordinary one, zero() empty
 //                      registers;
 //   terms(V, t)        the kTPV patterns of loaded registers;
-//   sload(i), sterm(R) the raw load of scalar term i and its pattern.
+//   sload(i), sterm(R) the raw load of scalar term i and its pattern;
+//                      sload_nt(i) the same load, non-temporal (the small
+//                      body reads every term once).
 // Loads and transforms are separate, so a transform (a product, a format
 // conversion) never forces an early wait on a prefetch.
 // ---------------------------------------------------------------------------
@@ -316,6 +318,7 @@ static __device__ ulonglong2 g_pad_tile[64 * kMaxVec];
 struct SrcF64 {
   const double *x;
   static constexpr int kTPV = 2;
+  static constexpr bool kPairs = true;        // the small body reads it in 16-byte pairs
   typedef const ulonglong2 *Ptr;
   typedef ulonglong2 Vec;
   typedef unsigned long long Raw;
@@ -332,6 +335,9 @@ struct SrcF64 {
     t[1] = v.y;
   }
   __device__ Raw sload(long long i) const { return as_bits(x[i]); }
+  __device__ Raw sload_nt(long long i) const {
+    return (unsigned long long)__builtin_nontemporal_load(reinterpret_cast<const long long *>(x) + i);
+  }
   __device__ unsigned long long sterm(Raw r) const { return r; }
 };
 
@@ -357,6 +363,7 @@ struct SrcDot {
   const double *x;
   const double *y;
   static constexpr int kTPV = 2;
+  static constexpr bool kPairs = false;
   struct Ptr {
     const ulonglong2 *p;
     const double *q;
@@ -401,6 +408,10 @@ struct SrcDot {
     t[1] = mul(v.a.y, v.b.y);
   }
   __device__ Raw sload(long long i) const { return Raw{as_bits(x[i]), as_bits(y[i])}; }
+  __device__ Raw sload_nt(long long i) const {
+    return Raw{(unsigned long long)__builtin_nontemporal_load(reinterpret_cast<const long long *>(x) + i),
+               (unsigned long long)__builtin_nontemporal_load(reinterpret_cast<const long long *>(y) + i)};
+  }
   __device__ unsigned long long sterm(Raw r) const { return mul(r.a, r.b); }
 };
 
@@ -422,8 +433,12 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 // binary32 sums is the narrow accumulator below).
 struct SrcF32 {
   const float *x;
+  static constexpr bool kPairs = false;
   typedef unsigned int Raw;
   __device__ Raw sload(long long i) const { return __float_as_uint(x[i]); }
+  __device__ Raw sload_nt(long long i) const {
+    return __builtin_nontemporal_load(reinterpret_cast<const unsigned int *>(x) + i);
+  }
   __device__ unsigned long long sterm(Raw r) const { return f32_to_f64_bits(r); }
 };
 
@@ -435,6 +450,7 @@ struct SrcF32 {
 struct SrcDotF32 {
   const float *x;
   const float *y;
+  static constexpr bool kPairs = false;
   struct Raw {
     unsigned int a, b;
   };
@@ -442,6 +458,10 @@ struct SrcDotF32 {
     return as_bits(__longlong_as_double((long long)u) * __longlong_as_double((long long)v));
   }
   __device__ Raw sload(long long i) const { return Raw{__float_as_uint(x[i]), __float_as_uint(y[i])}; }
+  __device__ Raw sload_nt(long long i) const {
+    return Raw{__builtin_nontemporal_load(reinterpret_cast<const unsigned int *>(x) + i),
+               __builtin_nontemporal_load(reinterpret_cast<const unsigned int *>(y) + i)};
+  }
   __device__ unsigned long long sterm(Raw r) const { return mul(f32_to_f64_bits(r.a), f32_to_f64_bits(r.b)); }
 };
 
@@ -1078,9 +1098,10 @@ __device__ __forceinline__ void carry_step(long long *c, int lane) {
 // The small-accumulator body of one wavefront.  The wave's accumulator is
 // COPIES copies of 68 chunks (small_acc_words<COPIES>() words in LDS); lane l
 // adds into copy l % COPIES, so the 64 lanes' adds to one chunk land on
-// several addresses instead of one (same-address LDS atomics serialise,
-// which binds when many wavefronts share a compute unit).  The copies sit
-// 544 bytes apart, on different banks.
+// several addresses instead of one (same-address LDS atomics serialise).
+// The copies sit 544 bytes apart (copy-major: they measured fewer LDS bank
+// conflicts than copies interleaved per chunk).  After small_wave_accumulate
+// the first 68 words hold the plain 68 chunks.
 template <int COPIES>
 constexpr int small_acc_words() { return 68 * COPIES; }
 
@@ -1098,36 +1119,41 @@ __device__ __forceinline__ void small_wave_zero(long long *acc, unsigned long lo
 
 // Each lane takes kSmallU terms per batch (term base + 64 j + lane); two
 // batches of registers alternate, so the next batch's loads are in flight
-// while the current one is added.  Load indices are clamped to the last
-// term, so every load is issued unconditionally and the compiler's wait
-// counts stay exact; clamped lanes add nothing.
+// while the current one is added.  A whole batch (base + 64 kSmallU <= hi)
+// is loaded from one address per lane with constant offsets.  In the last,
+// partial batch the load indices are clamped to the last term, so every
+// load is still issued unconditionally and the compiler's wait counts stay
+// exact; clamped lanes add nothing.
 constexpr int kSmallU = 8;
 template <class Src>
 __device__ __forceinline__ void small_batch_load(typename Src::Raw (&b)[kSmallU], const Src &src, long long base,
-                                                 long long last, int lane) {
+                                                 long long hi, int lane) {
+  if (base + 64 * kSmallU <= hi) {
 #pragma unroll
-  for (int j = 0; j < kSmallU; j++) {
-    long long i = base + (long long)j * 64 + lane;
-    i = i < last ? i : last;
-    b[j] = src.sload(i);
+    for (int j = 0; j < kSmallU; j++) b[j] = src.sload_nt(base + lane + (long long)j * 64);
+  } else {
+    const long long last = hi - 1;
+#pragma unroll
+    for (int j = 0; j < kSmallU; j++) {
+      long long i = base + (long long)j * 64 + lane;
+      i = i < last ? i : last;
+      b[j] = src.sload_nt(i);
+    }
   }
   __builtin_amdgcn_sched_barrier(0);
 }
-template <class Src>
-__device__ __forceinline__ void small_batch_add(long long *mine, unsigned long long *spec, const Src &src,
-                                                const typename Src::Raw (&b)[kSmallU], long long base, long long hi,
-                                                int lane) {
-  unsigned long long t[kSmallU];
+// Add one lane's K terms (bit patterns; a 0 adds nothing).  A batch of
+// finite terms takes one branch-free path; only a batch holding an infinity
+// or NaN goes term by term.
+template <int K>
+__device__ __forceinline__ void small_terms_add(long long *mine, unsigned long long *spec,
+                                                const unsigned long long (&t)[K]) {
   bool special = false;
 #pragma unroll
-  for (int j = 0; j < kSmallU; j++) {
-    t[j] = src.sterm(b[j]);
-    special |= is_special(t[j]);
-  }
-  if (base + 64 * kSmallU <= hi && !__any(special)) {
-    // a whole batch of finite terms (the common case): no per-term branch
+  for (int j = 0; j < K; j++) special |= is_special(t[j]);
+  if (!__any(special)) {
 #pragma unroll
-    for (int j = 0; j < kSmallU; j++) {
+    for (int j = 0; j < K; j++) {
       int h;
       long long plo, phi;
       term_pieces(t[j], h, plo, phi);
@@ -1137,20 +1163,69 @@ __device__ __forceinline__ void small_batch_add(long long *mine, unsigned long l
     return;
   }
 #pragma unroll
-  for (int j = 0; j < kSmallU; j++) {
-    const long long i = base + (long long)j * 64 + lane;
-    if (i < hi) {
-      if (is_special(t[j])) {
-        note_special(t[j], &spec[0], &spec[1], &spec[2]);
-      } else {
-        int h;
-        long long plo, phi;
-        term_pieces(t[j], h, plo, phi);
-        atomicAdd((unsigned long long *)&mine[h], (unsigned long long)plo);
-        atomicAdd((unsigned long long *)&mine[h + 1], (unsigned long long)phi);
-      }
+  for (int j = 0; j < K; j++) {
+    if (is_special(t[j])) {
+      note_special(t[j], &spec[0], &spec[1], &spec[2]);
+    } else {
+      int h;
+      long long plo, phi;
+      term_pieces(t[j], h, plo, phi);
+      atomicAdd((unsigned long long *)&mine[h], (unsigned long long)plo);
+      atomicAdd((unsigned long long *)&mine[h + 1], (unsigned long long)phi);
     }
   }
+}
+
+// Add one batch.  Lanes past hi in the last batch carry the term 0.
+template <class Src>
+__device__ __forceinline__ void small_batch_add(long long *mine, unsigned long long *spec, const Src &src,
+                                                const typename Src::Raw (&b)[kSmallU], long long base, long long hi,
+                                                int lane) {
+  unsigned long long t[kSmallU];
+  const bool whole = base + 64 * kSmallU <= hi;
+#pragma unroll
+  for (int j = 0; j < kSmallU; j++) {
+    t[j] = src.sterm(b[j]);
+    if (!whole && base + (long long)j * 64 + lane >= hi) t[j] = 0ull;
+  }
+  small_terms_add(mine, spec, t);
+}
+
+// Sources with kPairs (a single binary64 array) are read two terms per
+// 16-byte non-temporal load, as the large kernel reads them: a batch is
+// kSmallU / 2 vectors per lane (vector v = vb + 64 j + lane of the aligned
+// part, terms 2v and 2v + 1), so a batch still holds kSmallU terms per lane.
+constexpr int kPairV = kSmallU / 2;
+template <class Src>
+__device__ __forceinline__ void pair_batch_load(ulonglong2 (&v)[kPairV], const Src &src, long long a, long long vb,
+                                                long long nv, int lane) {
+  const ulonglong2 *p = reinterpret_cast<const ulonglong2 *>(src.x + a);
+  if (vb + 64 * kPairV <= nv) {
+#pragma unroll
+    for (int j = 0; j < kPairV; j++) v[j] = stream_load(p + vb + lane + (long long)j * 64);
+  } else {
+    const long long last = nv - 1;
+#pragma unroll
+    for (int j = 0; j < kPairV; j++) {
+      long long i = vb + (long long)j * 64 + lane;
+      i = i < last ? i : last;
+      v[j] = stream_load(p + i);
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+}
+template <class Src>
+__device__ __forceinline__ void pair_batch_add(long long *mine, unsigned long long *spec, const Src &src,
+                                               const ulonglong2 (&v)[kPairV], long long vb, long long nv, int lane) {
+  unsigned long long t[kSmallU];
+  const bool whole = vb + 64 * kPairV <= nv;
+#pragma unroll
+  for (int j = 0; j < kPairV; j++) {
+    const bool off = !whole && vb + (long long)j * 64 + lane >= nv;
+    t[2 * j] = off ? 0ull : src.sterm(v[j].x);
+    t[2 * j + 1] = off ? 0ull : src.sterm(v[j].y);
+  }
+  small_terms_add(mine, spec, t);
 }
 template <int COPIES>
 __device__ __forceinline__ void small_carry_all(long long *acc, int lane) {
@@ -1158,50 +1233,72 @@ __device__ __forceinline__ void small_carry_all(long long *acc, int lane) {
   for (int c = 0; c < COPIES; c++) carry_step(acc + 68 * c, lane);
 }
 
-// Wave adds the source's terms lo .. hi into acc (small_acc_words<COPIES>()
-// words, zeroed by the caller); specials into spec[3].  On return the sum is
-// in the first 68 words, each below COPIES * 2^33 in magnitude.  With
-// `direct` (the caller rounds the result and merges it nowhere), a range of
-// fewer than 1024 terms skips the carry steps of the copies: every term adds
-// at most one piece below 2^52 to a given chunk, so each chunk's total over
-// all copies stays below 1023 * 2^52 < 2^62, which the rounding accepts.
+// One wave's pass over a range [lo, hi) (hi > lo) of a kPairs source, split
+// in two so that a wave can issue a range's first loads early (while it still
+// finishes another range): pair_range_begin issues the loads of the first
+// batch and of the two edge terms (one before the first 16-byte boundary,
+// one after the last whole vector, added by lanes 0 and 1), and
+// pair_range_add adds every term of the range into the accumulator copies.
+template <class Src>
+struct PairRange {
+  long long a;                  // first term of the aligned part
+  long long nv;                 // whole 16-byte vectors from a
+  bool fix;                     // this lane adds an edge term
+  typename Src::Raw fr;         // that term, as loaded
+  ulonglong2 A[kPairV];         // the first batch
+};
+template <class Src>
+__device__ __forceinline__ void pair_range_begin(PairRange<Src> &r, const Src &src, long long lo, long long hi,
+                                                 int lane) {
+  const long long head = (reinterpret_cast<uintptr_t>(src.x + lo) & 15) ? 1 : 0;
+  r.a = lo + head < hi ? lo + head : hi;
+  r.nv = (hi - r.a) / 2;
+  const long long tail = (hi - r.a) - 2 * r.nv;
+  r.fix = (lane == 0 && head) || (lane == 1 && tail);
+  // the edge loads are clamped into the range, so issued unconditionally
+  r.fr = src.sload_nt(lane == 1 ? hi - 1 : lo);
+  if (r.nv > 0) pair_batch_load(r.A, src, r.a, 0, r.nv, lane);
+}
 template <int COPIES, class Src>
-__device__ __forceinline__ void small_wave_accumulate(long long *acc, unsigned long long *spec, const Src &src,
-                                                      long long lo, long long hi, int lane, bool direct = false) {
-  // a copy's chunk receives at most 64 / COPIES pieces below 2^52 per
-  // 64-term step; a carry step after every kEvery batches keeps it below
-  // 1536 * 2^52 < 2^63
-  constexpr int kEvery = 3 * COPIES;
-  static_assert(64 % COPIES == 0 && kEvery * kSmallU * (64 / COPIES) <= 1536, "carry interval");
+__device__ __forceinline__ void pair_range_add(long long *acc, unsigned long long *spec, const Src &src,
+                                               PairRange<Src> &r, int lane) {
+  constexpr int kEvery = 3 * COPIES;             // as in small_wave_accumulate
   long long *mine = acc + 68 * (lane % COPIES);
-  if (hi > lo) {
-    constexpr long long kB = 64 * kSmallU;
-    const long long last = hi - 1;
-    typename Src::Raw A[kSmallU], B[kSmallU];
-    small_batch_load(A, src, lo, last, lane);
+  if (r.nv > 0) {
+    constexpr long long kVB = 64 * kPairV;
+    ulonglong2 B[kPairV];
     int batches = 0;
-    for (long long base = lo;;) {
-      small_batch_load(B, src, base + kB, last, lane);
-      small_batch_add(mine, spec, src, A, base, hi, lane);
-      base += kB;
+    for (long long vb = 0;;) {
+      pair_batch_load(B, src, r.a, vb + kVB, r.nv, lane);
+      pair_batch_add(mine, spec, src, r.A, vb, r.nv, lane);
+      vb += kVB;
       if (++batches == kEvery) {
         batches = 0;
         small_carry_all<COPIES>(acc, lane);
       }
-      if (base >= hi) break;
-      small_batch_load(A, src, base + kB, last, lane);
-      small_batch_add(mine, spec, src, B, base, hi, lane);
-      base += kB;
+      if (vb >= r.nv) break;
+      pair_batch_load(r.A, src, r.a, vb + kVB, r.nv, lane);
+      pair_batch_add(mine, spec, src, B, vb, r.nv, lane);
+      vb += kVB;
       if (++batches == kEvery) {
         batches = 0;
         small_carry_all<COPIES>(acc, lane);
       }
-      if (base >= hi) break;
+      if (vb >= r.nv) break;
     }
   }
-  if (!(direct && hi - lo < 1024)) small_carry_all<COPIES>(acc, lane);
+  const unsigned long long ft[1] = {r.fix ? src.sterm(r.fr) : 0ull};
+  small_terms_add(mine, spec, ft);
+}
+
+// The end of a wave's sum: carry steps of the copies (skipped when the range
+// had fewer than 1024 terms and `direct`; see small_wave_accumulate), then
+// the copies added into the first 68 words.
+template <int COPIES>
+__device__ __forceinline__ void small_wave_finish(long long *acc, int lane, bool skip_carry) {
+  if (!skip_carry) small_carry_all<COPIES>(acc, lane);
   if (COPIES > 1) {
-    // add the copies into the first: every copy is below 2^33 after its carry
+    // every copy is below 2^33 after its carry (below 1023 * 2^52 without)
     __builtin_amdgcn_wave_barrier();
     long long t0 = 0, t1 = 0;
 #pragma unroll
@@ -1214,6 +1311,61 @@ __device__ __forceinline__ void small_wave_accumulate(long long *acc, unsigned l
     if (lane < 4) acc[64 + lane] = t1;
     __builtin_amdgcn_wave_barrier();
   }
+}
+
+// Wave adds the source's terms lo .. hi into acc (small_acc_words<COPIES>()
+// words, zeroed by the caller); specials into spec[3].  On return the sum is
+// in the first 68 words, each below COPIES * 2^33 in magnitude.  With
+// `direct` (the caller rounds the result and merges it nowhere), a range of
+// fewer than 1024 terms skips the carry steps of the copies: every term adds
+// at most one piece below 2^52 to a given chunk, so each chunk's total over
+// all copies stays below 1023 * 2^52 < 2^62, which the rounding accepts.
+// With ZERO the accumulator is cleared here, after the first batch's loads
+// are issued, so that the clearing overlaps their latency (the caller then
+// need not zero it).
+template <int COPIES, class Src, bool ZERO = false>
+__device__ __forceinline__ void small_wave_accumulate(long long *acc, unsigned long long *spec, const Src &src,
+                                                      long long lo, long long hi, int lane, bool direct = false) {
+  // a copy's chunk receives at most 64 / COPIES pieces below 2^52 per
+  // 64-term step; a carry step after every kEvery batches keeps it below
+  // 1536 * 2^52 < 2^63
+  constexpr int kEvery = 3 * COPIES;
+  static_assert(64 % COPIES == 0 && kEvery * kSmallU * (64 / COPIES) <= 1536, "carry interval");
+  long long *mine = acc + 68 * (lane % COPIES);
+  if (ZERO && !(hi > lo)) small_wave_zero<COPIES>(acc, spec, lane);
+  if constexpr (Src::kPairs) {
+    if (hi > lo) {
+      PairRange<Src> r;
+      pair_range_begin(r, src, lo, hi, lane);
+      if (ZERO) small_wave_zero<COPIES>(acc, spec, lane);
+      pair_range_add<COPIES>(acc, spec, src, r, lane);
+    }
+  } else if (hi > lo) {
+    constexpr long long kB = 64 * kSmallU;
+    typename Src::Raw A[kSmallU], B[kSmallU];
+    small_batch_load(A, src, lo, hi, lane);
+    if (ZERO) small_wave_zero<COPIES>(acc, spec, lane);
+    int batches = 0;
+    for (long long base = lo;;) {
+      small_batch_load(B, src, base + kB, hi, lane);
+      small_batch_add(mine, spec, src, A, base, hi, lane);
+      base += kB;
+      if (++batches == kEvery) {
+        batches = 0;
+        small_carry_all<COPIES>(acc, lane);
+      }
+      if (base >= hi) break;
+      small_batch_load(A, src, base + kB, hi, lane);
+      small_batch_add(mine, spec, src, B, base, hi, lane);
+      base += kB;
+      if (++batches == kEvery) {
+        batches = 0;
+        small_carry_all<COPIES>(acc, lane);
+      }
+      if (base >= hi) break;
+    }
+  }
+  small_wave_finish<COPIES>(acc, lane, direct && hi - lo < 1024);
 }
 
 // ---------------------------------------------------------------------------
@@ -1269,11 +1421,11 @@ struct FinAcc {
   GlobalAcc *acc;
   __device__ void operator()(long long *c, unsigned long long *spec) const {
     const int tid = threadIdx.x;
-    if (tid < 68) c[tid] += (long long)acc->chunk[tid];
+    for (int i = tid; i < 68; i += blockDim.x) c[i] += (long long)acc->chunk[i];
     __syncthreads();
     if (tid < 64) carry_step(c, tid);
     __syncthreads();
-    if (tid < 68) acc->chunk[tid] = (unsigned long long)c[tid];
+    for (int i = tid; i < 68; i += blockDim.x) acc->chunk[i] = (unsigned long long)c[i];
     if (tid == 0) {
       acc->pos_inf |= spec[0];
       acc->neg_inf |= spec[1];

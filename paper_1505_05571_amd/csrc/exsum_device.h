@@ -137,19 +137,22 @@ __device__ __forceinline__ void mantissa_sum_pieces(unsigned int ix, unsigned lo
 
 // ---- one term -> two small-chunk pieces (the small-superaccumulator add) ---
 
-// For a finite term: chunk index h = e_eff>>5, low piece (< 2^32) for chunk h
-// and high piece (< 2^52) for chunk h+1, both already signed.
+// For a finite term: chunk index h = e_eff>>5 and two pieces with
+// plo + phi 2^32 = (-1)^s M 2^(e_eff & 31): the signed significand M' =
+// (-1)^s M is shifted left by e_eff & 31, plo is the low 32 bits of that
+// (0 <= plo < 2^32, for chunk h) and phi the rest, an arithmetic shift
+// (|phi| < 2^52, for chunk h+1).  The sign is applied once, without a branch
+// (Discussion), before the split.
 __device__ __forceinline__ void term_pieces(unsigned long long b, int &h, long long &plo, long long &phi) {
   const unsigned int e = (unsigned int)(b >> 52) & 2047u;
   const unsigned long long M = (b & ((1ull << 52) - 1)) | ((unsigned long long)(e != 0) << 52);
   const unsigned int e_eff = e ? e : 1u;
   const unsigned int lo = e_eff & 31u;
   h = (int)(e_eff >> 5);
-  const long long low = (long long)((M << lo) & 0xFFFFFFFFull);
-  const long long high = (long long)(M >> (32 - lo));
-  const long long neg = (long long)b >> 63;          // branch-free conditional negate
-  plo = (low ^ neg) - neg;
-  phi = (high ^ neg) - neg;
+  const long long neg = (long long)b >> 63;          // 0 or -1
+  const long long Ms = (long long)((M ^ (unsigned long long)neg) - (unsigned long long)neg);
+  plo = (long long)(unsigned int)((unsigned int)(unsigned long long)Ms << lo);
+  phi = Ms >> (32 - lo);
 }
 
 __device__ __forceinline__ bool is_special(unsigned long long b) {
@@ -294,19 +297,28 @@ __device__ inline WaveMag wave_magnitude(const long long *c, int lane) {
   // each row of 16 lanes (row_shr 1, 2, 4, 8), then row 0's total into row
   // 1 and row 2's into row 3 (row_bcast:15), then rows 0-1's into rows 2-3
   // (row_bcast:31); lanes without a source compose with the identity map
-  constexpr unsigned int kId = 0u | (1u << 2) | (2u << 4);   // c -> c
-  unsigned int F = carry_map(A);
-  F = carry_compose(F, dpp_u32<0x111>(kId, F));
-  F = carry_compose(F, dpp_u32<0x112>(kId, F));
-  F = carry_compose(F, dpp_u32<0x114>(kId, F));
-  F = carry_compose(F, dpp_u32<0x118>(kId, F));
-  F = carry_compose(F, dpp_u32<0x142, 0xA>(kId, F));
-  F = carry_compose(F, dpp_u32<0x143, 0xC>(kId, F));
-  const unsigned int Fprev = dpp_u32<0x138>(kId, F);          // lane 0: the identity, carry in 0
-  const int cin = carry_apply(Fprev, 0);
-  unsigned int dA = (unsigned int)(A + cin);
+  // (when no digit is -1 or 2^32, which is the common case, no digit
+  // passes a carry on and the scan is skipped)
+  unsigned int dA;
+  long long cy;
+  if (__ballot(A == -1ll || A == 0x100000000ll) == 0ull) {
+    dA = (unsigned int)A;
+    cy = 0;
+  } else {
+    constexpr unsigned int kId = 0u | (1u << 2) | (2u << 4);   // c -> c
+    unsigned int F = carry_map(A);
+    F = carry_compose(F, dpp_u32<0x111>(kId, F));
+    F = carry_compose(F, dpp_u32<0x112>(kId, F));
+    F = carry_compose(F, dpp_u32<0x114>(kId, F));
+    F = carry_compose(F, dpp_u32<0x118>(kId, F));
+    F = carry_compose(F, dpp_u32<0x142, 0xA>(kId, F));
+    F = carry_compose(F, dpp_u32<0x143, 0xC>(kId, F));
+    const unsigned int Fprev = dpp_u32<0x138>(kId, F);          // lane 0: the identity, carry in 0
+    const int cin = carry_apply(Fprev, 0);
+    dA = (unsigned int)(A + cin);
+    cy = carry_apply((unsigned int)__builtin_amdgcn_readlane((int)F, 63), 0);
+  }
   // digits 64, 65 and the top take the remaining carries in order
-  long long cy = carry_apply((unsigned int)__builtin_amdgcn_readlane((int)F, 63), 0);
   const long long v64 = (long long)readlane_u64((unsigned long long)B, 0) + cy;
   cy = v64 >> 32;
   const long long v65 = (long long)readlane_u64((unsigned long long)B, 1) + cy;

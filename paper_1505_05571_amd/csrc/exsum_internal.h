@@ -22,6 +22,7 @@ struct Workspace {
   // the short-segment partition's chunk weights (kMaxGrid words)
   GlobalAcc *seg_accs = nullptr;
   long long *seg_chunks = nullptr;
+  void *seg_ctl = nullptr;             // the persistent launch's cursor (seg_ctl_bytes())
 };
 
 // Host helpers (api.cpp): EXSUM_* status of a HIP error (clearing the HIP
@@ -74,6 +75,14 @@ size_t global_acc_bytes();
 hipError_t launch_segmented(const double *x, const int64_t *offsets, int64_t nseg, double *out,
                             GlobalAcc *accs, long long *chunks, hipStream_t s, int grid, int short_grid,
                             int64_t small_max, int precombine);
+// One persistent launch (block = 256, 512 or 1024 threads, `grid`
+// workgroups): long segments by term range with the large accumulator, then
+// short ones claimed by waves in units of `group` (1..64) segments from the
+// cursor in `ctl` (seg_ctl_bytes() of zeroed workspace, left zeroed).
+hipError_t launch_segmented_persistent(const double *x, const int64_t *offsets, int64_t nseg, double *out,
+                                       GlobalAcc *accs, void *ctl, hipStream_t s, int grid, int block,
+                                       int64_t small_max, int precombine, int group);
+size_t seg_ctl_bytes();
 hipError_t launch_check_offsets(const int64_t *offsets, int64_t nseg, int64_t n, int64_t *first_bad, hipStream_t s);
 int seg_short_block();
 

@@ -50,35 +50,20 @@ struct SegShared {
   long long red[16];                   // wave partial sums
 };
 
+// The long segments meeting workgroup w's term range [o0 + N*w/G,
+// o0 + N*(w+1)/G) of G = min(grid, N) workgroups, summed with the large
+// accumulator; a segment inside the range is rounded here, a segment cut by
+// range boundaries adds its piece into the slot of its first workgroup and
+// the piece that completes the ticket count rounds.  Called by every thread
+// of the workgroup; returns at once (uniformly) when there are no terms or
+// w >= G.
 template <int BLOCK, int VEC, int DEPTH>
-__global__ __launch_bounds__(BLOCK) void seg_long_kernel(const double *__restrict__ x,
-                                                         const long long *__restrict__ offsets, long long nseg,
-                                                         double *__restrict__ out, GlobalAcc *__restrict__ accs,
-                                                         long long small_max, int precombine,
-                                                         long long *__restrict__ chunks, int nchunks) {
-  __shared__ SegShared S;
+__device__ __forceinline__ void long_phase(SegShared &S, const double *__restrict__ x,
+                                           const long long *__restrict__ offsets, long long nseg,
+                                           double *__restrict__ out, GlobalAcc *__restrict__ accs,
+                                           long long small_max, int precombine) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // all lanes active here
-  if (chunks) {
-    // weights of the short kernel's chunks (segments [k*nseg/C, (k+1)*nseg/C))
-    for (long long k = blockIdx.x; k < nchunks; k += gridDim.x) {
-      const long long c0 = k * nseg / nchunks, c1 = (k + 1) * nseg / nchunks;
-      long long t = 0;
-      for (long long i = c0 + tid; i < c1; i += BLOCK) {
-        const long long len = offsets[i + 1] - offsets[i];
-        if (len <= small_max) t += len + kSegCost;
-      }
-      t = wave_sum_i64(t);
-      if (lane == 0) S.red[wave] = t;
-      __syncthreads();
-      if (tid == 0) {
-        long long u = 0;
-        for (int w = 0; w < BLOCK / 64; w++) u += S.red[w];
-        chunks[k] = u;
-      }
-      __syncthreads();
-    }
-  }
   const long long o0 = offsets[0], oN = offsets[nseg];
   const long long N = oN - o0;
   if (N <= 0) return;                                   // no terms: only empty (short) segments
@@ -127,7 +112,7 @@ __global__ __launch_bounds__(BLOCK) void seg_long_kernel(const double *__restric
     const int nb = (int)S.nb;
     for (int k = 0; k < nb; k++) {
       const long long s0 = S.off[k], s1 = S.off[k + 1];
-      if (s1 - s0 <= small_max) continue;              // short: the other kernel's
+      if (s1 - s0 <= small_max) continue;              // short: summed elsewhere
       const long long a = s0 > lo_w ? s0 : lo_w;
       const long long b = s1 < hi_w ? s1 : hi_w;
       accumulate_range<BLOCK, VEC, DEPTH, kCarryMode>(S.L, SrcF64{x}, a, b, precombine, tile);
@@ -149,6 +134,38 @@ __global__ __launch_bounds__(BLOCK) void seg_long_kernel(const double *__restric
     i += cnt;
     __syncthreads();
   }
+}
+
+template <int BLOCK, int VEC, int DEPTH>
+__global__ __launch_bounds__(BLOCK) void seg_long_kernel(const double *__restrict__ x,
+                                                         const long long *__restrict__ offsets, long long nseg,
+                                                         double *__restrict__ out, GlobalAcc *__restrict__ accs,
+                                                         long long small_max, int precombine,
+                                                         long long *__restrict__ chunks, int nchunks) {
+  __shared__ SegShared S;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // all lanes active here
+  if (chunks) {
+    // weights of the short kernel's chunks (segments [k*nseg/C, (k+1)*nseg/C))
+    for (long long k = blockIdx.x; k < nchunks; k += gridDim.x) {
+      const long long c0 = k * nseg / nchunks, c1 = (k + 1) * nseg / nchunks;
+      long long t = 0;
+      for (long long i = c0 + tid; i < c1; i += BLOCK) {
+        const long long len = offsets[i + 1] - offsets[i];
+        if (len <= small_max) t += len + kSegCost;
+      }
+      t = wave_sum_i64(t);
+      if (lane == 0) S.red[wave] = t;
+      __syncthreads();
+      if (tid == 0) {
+        long long u = 0;
+        for (int w = 0; w < BLOCK / 64; w++) u += S.red[w];
+        chunks[k] = u;
+      }
+      __syncthreads();
+    }
+  }
+  long_phase<BLOCK, VEC, DEPTH>(S, x, offsets, nseg, out, accs, small_max, precombine);
 }
 
 constexpr int kShortCopies = 8;
@@ -324,19 +341,207 @@ __global__ __launch_bounds__(BLOCK) void seg_short_kernel(const double *__restri
     }
     total = __builtin_amdgcn_readfirstlane(total);
     __syncthreads();
-    for (;;) {
-      // every lane adds 1, so one claim advances the counter by 64 and the
-      // first lane's old value (wave-uniform) names the claimed entry; no
-      // value of one lane is broadcast, and the loop stays scalar
+    // Claim the next entry of the round.  Every lane adds 1, so one claim
+    // advances the counter by 64 and the first lane's old value
+    // (wave-uniform) names the claimed entry; no value of one lane is
+    // broadcast, and every loop and branch below stays scalar.
+    auto claim = [&](int &j, long long &a, long long &b) -> bool {
       const int k = __builtin_amdgcn_readfirstlane(atomicAdd(&S.cnt, 1)) >> 6;
-      if (k >= total) break;
-      const int j = __builtin_amdgcn_readfirstlane(S.ord[k]);
-      const long long a = uniform_i64(S.lo[j]), b = uniform_i64(S.hi[j]);
+      if (k >= total) return false;
+      j = __builtin_amdgcn_readfirstlane(S.ord[k]);
+      a = uniform_i64(S.lo[j]);
+      b = uniform_i64(S.hi[j]);
+      return true;
+    };
+    // A wave holds two segments: while it sums one, the first loads of the
+    // next are already in flight, so it never waits a full memory latency
+    // at a segment start.
+    const SrcF64 src{x};
+    int j0 = 0, j1 = 0;
+    long long a0 = 0, b0 = 0, a1 = 0, b1 = 0;
+    PairRange<SrcF64> R0, R1;
+    bool h0 = claim(j0, a0, b0);
+    if (h0 && b0 > a0) pair_range_begin(R0, src, a0, b0, lane);
+    small_wave_zero<kShortCopies>(acc, spec, lane);
+    while (h0) {
+      const bool h1 = claim(j1, a1, b1);
+      if (h1 && b1 > a1) pair_range_begin(R1, src, a1, b1, lane);
+      if (b0 > a0) pair_range_add<kShortCopies>(acc, spec, src, R0, lane);
+      small_wave_finish<kShortCopies>(acc, lane, b0 - a0 < 1024);
+      wave_merge_and_round(acc, spec, nullptr, 1u, &out[r0 + j0], lane);
       small_wave_zero<kShortCopies>(acc, spec, lane);
-      small_wave_accumulate<kShortCopies>(acc, spec, SrcF64{x}, a, b, lane, true);
-      wave_merge_and_round(acc, spec, nullptr, 1u, &out[r0 + j], lane);
+      if (!h1) break;
+      h0 = claim(j0, a0, b0);
+      if (h0 && b0 > a0) pair_range_begin(R0, src, a0, b0, lane);
+      if (b1 > a1) pair_range_add<kShortCopies>(acc, spec, src, R1, lane);
+      small_wave_finish<kShortCopies>(acc, lane, b1 - a1 < 1024);
+      wave_merge_and_round(acc, spec, nullptr, 1u, &out[r0 + j1], lane);
+      small_wave_zero<kShortCopies>(acc, spec, lane);
     }
     __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One persistent launch for the whole batch.  Every workgroup first sums the
+// long segments of its term range (long_phase, as above); then every wave,
+// on its own, claims units of short segments until none are left.  A unit is
+// (class c, group g): the segments [g*group, (g+1)*group) whose length falls
+// in class c (at least 4096 terms, or fewer; at most small_max).  The groups are dealt to kCursors cursors, group g to cursor
+// g mod kCursors, and each cursor hands out all its units of the longer
+// class first: the longest short segments start first and the last units
+// handed out hold only shorter ones, so no compute unit waits long for
+// another at the end, and a workgroup whose term range held few
+// long-segment terms goes on to short ones at once.  A wave claims from the
+// cursor of its own XCD (workgroups are dealt to the eight XCDs in turn)
+// and, once that is exhausted, from the others, so the claims spread over
+// kCursors separate addresses.  Each claimed segment is summed whole by the
+// wave with the small superaccumulator and rounded there (Performance
+// evaluations: the small method for short sums, the large one for long
+// sums).  A wave claims its next unit and issues that unit's offset loads
+// before it sums the current one, so neither latency stands between units.
+//
+// The cursors and a count of finished waves live in the workspace, zeroed.
+// A wave counts itself finished after the claims that found every cursor
+// exhausted, so the last one to finish knows every claim has been made and
+// resets them all: the next launch on the stream starts clean (and a
+// captured graph can be replayed).  Claims are made by lane 0 and read back
+// with readfirstlane, so every loop below is wave-uniform; nothing waits on
+// another wave or workgroup.
+// ---------------------------------------------------------------------------
+constexpr int kCursors = 8;
+// Length classes of the cursors' order: segments of at least kClassA terms,
+// then all shorter ones together (handing out the shortest ones last, on
+// their own, left every wave on latency-bound tiny sums at the end).
+constexpr int kUnitClasses = 2;
+struct SegCtl {
+  unsigned int cursor[kCursors][32];    // one 128-byte line each
+  unsigned int done;                    // waves that have made their last claim
+};
+
+template <int NW>
+struct PersistShort {
+  long long acc[NW][small_acc_words<kShortCopies>()];
+  unsigned long long spec[NW][4];
+};
+template <int NW>
+union PersistShared {
+  SegShared L;                          // the long phase
+  PersistShort<NW> S;                   // the short phase
+};
+
+// A claimed unit: its first segment and class (wave-uniform; cls < 0 means
+// every cursor was exhausted), and this lane's segment (have: it exists).
+struct SegUnit {
+  long long g0;
+  long long cls;
+  long long s0, s1;
+  bool have;
+};
+
+struct UnitClaimer {
+  SegCtl *ctl;
+  long long ngroups, group;
+  int home;                             // this workgroup's XCD's cursor
+  int t;                                // cursors home .. home+t-1 (mod kCursors) are exhausted
+  // Claim a unit (blocking on the atomic); cls < 0 when none is left.
+  __device__ void claim(SegUnit &u, int lane) {
+    u.cls = -1;
+    u.g0 = 0;
+    while (t < kCursors) {
+      const int k = (home + t) % kCursors;
+      unsigned int v = 0;
+      if (lane == 0) v = atomicAdd(&ctl->cursor[k][0], 1u);
+      const long long vv = (long long)(unsigned int)__builtin_amdgcn_readfirstlane((int)v);
+      // cursor k holds the groups k, k + kCursors, ... below ngroups
+      const long long ngk = (ngroups - k + kCursors - 1) / kCursors;
+      if (vv < kUnitClasses * ngk) {
+        u.cls = vv / ngk;
+        u.g0 = ((vv - u.cls * ngk) * kCursors + k) * group;
+        return;
+      }
+      t++;
+    }
+  }
+};
+
+// Issue the unit's offset loads (lanes below `group`); their values are
+// first used by unit_run.
+__device__ __forceinline__ void unit_load(SegUnit &u, const long long *__restrict__ offsets, long long nseg,
+                                          long long group, int lane) {
+  const long long i = u.g0 + lane;
+  u.have = u.cls >= 0 && lane < group && i < nseg;
+  u.s0 = 0;
+  u.s1 = 0;
+  if (u.have) {
+    u.s0 = offsets[i];
+    u.s1 = offsets[i + 1];
+  }
+}
+
+// Sum and round the unit's segments of its class, one after another;
+// `before_last` runs once, just before the last of them (at once if there
+// are none), so the next unit is claimed late enough that a wave never sits
+// on a unit another wave could have taken, yet its latency still hides
+// behind one segment.
+template <class Hook>
+__device__ __forceinline__ void unit_run(const SegUnit &u, const SrcF64 &src, double *__restrict__ out,
+                                         long long small_max, long long *acc, unsigned long long *spec, int lane,
+                                         const Hook &before_last) {
+  const long long len = u.s1 - u.s0;
+  const long long c = len >= kClassA ? 0 : 1;
+  unsigned long long m = __ballot(u.have && len <= small_max && c == u.cls);
+  if (m == 0ull) before_last();
+  for (; m; m &= m - 1) {
+    if ((m & (m - 1)) == 0ull) before_last();
+    const int k = __ffsll((long long)m) - 1;
+    const long long a = (long long)readlane_u64((unsigned long long)u.s0, k);
+    const long long b = (long long)readlane_u64((unsigned long long)u.s1, k);
+    small_wave_zero<kShortCopies>(acc, spec, lane);
+    small_wave_accumulate<kShortCopies>(acc, spec, src, a, b, lane, true);
+    wave_merge_and_round(acc, spec, nullptr, 1u, &out[u.g0 + k], lane);
+  }
+}
+
+template <int BLOCK, int VEC, int DEPTH>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK <= 256 ? 2 : 4)))
+void seg_persistent_kernel(const double *__restrict__ x, const long long *__restrict__ offsets, long long nseg,
+                           double *__restrict__ out, GlobalAcc *__restrict__ accs, long long small_max,
+                           int precombine, SegCtl *__restrict__ ctl, int group) {
+  constexpr int NW = BLOCK / 64;
+  __shared__ PersistShared<NW> U;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // all lanes active here
+  long_phase<BLOCK, VEC, DEPTH>(U.L, x, offsets, nseg, out, accs, small_max, precombine);
+  __syncthreads();                                    // the long phase's LDS is reused below
+
+  long long *acc = U.S.acc[wave];
+  unsigned long long *spec = U.S.spec[wave];
+  const SrcF64 src{x};
+  // a wave starts at the cursor of its workgroup's XCD
+  UnitClaimer cl{ctl, (nseg + group - 1) / group, group, (int)(blockIdx.x % kCursors), 0};
+  SegUnit A, B;
+  cl.claim(A, lane);
+  unit_load(A, offsets, nseg, group, lane);
+  auto next_b = [&]() {
+    cl.claim(B, lane);
+    unit_load(B, offsets, nseg, group, lane);
+  };
+  auto next_a = [&]() {
+    cl.claim(A, lane);
+    unit_load(A, offsets, nseg, group, lane);
+  };
+  while (A.cls >= 0) {
+    unit_run(A, src, out, small_max, acc, spec, lane, next_b);
+    if (B.cls < 0) break;
+    unit_run(B, src, out, small_max, acc, spec, lane, next_a);
+  }
+  if (lane == 0) {
+    const unsigned int total = gridDim.x * (unsigned int)NW;
+    if (atomicAdd(&ctl->done, 1u) == total - 1u) {
+      for (int k = 0; k < kCursors; k++) atomicExch(&ctl->cursor[k][0], 0u);
+      atomicExch(&ctl->done, 0u);
+    }
   }
 }
 
@@ -394,6 +599,28 @@ hipError_t launch_check_offsets(const int64_t *offsets, int64_t nseg, int64_t n,
                      (long long)nseg, (long long)n, fb);
   return hipGetLastError();
 }
+
+hipError_t launch_segmented_persistent(const double *x, const int64_t *offsets, int64_t nseg, double *out,
+                                       GlobalAcc *accs, void *ctl, hipStream_t s, int grid, int block,
+                                       int64_t small_max, int precombine, int group) {
+  if (grid < 1) grid = 1;
+  if (group < 1) group = 1;
+  if (group > 64) group = 64;
+#define EXSUM_SEG_LAUNCH(B, V, D)                                                                              \
+  if (block == B) {                                                                                            \
+    hipLaunchKernelGGL((seg_persistent_kernel<B, V, D>), dim3(grid), dim3(B), 0, s, x, (const long long *)offsets, \
+                       (long long)nseg, out, accs, (long long)small_max, precombine, static_cast<SegCtl *>(ctl),   \
+                       group);                                                                                 \
+    return hipGetLastError();                                                                                  \
+  }
+  EXSUM_SEG_LAUNCH(256, 4, 2)
+  EXSUM_SEG_LAUNCH(512, 2, 2)
+  EXSUM_SEG_LAUNCH(1024, 2, 2)
+#undef EXSUM_SEG_LAUNCH
+  return hipErrorInvalidValue;
+}
+
+size_t seg_ctl_bytes() { return (sizeof(SegCtl) + 255) / 256 * 256; }
 
 int seg_short_block() { return kShortBlock; }
 

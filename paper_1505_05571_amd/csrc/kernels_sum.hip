@@ -81,6 +81,27 @@ __global__ __launch_bounds__(BLOCK) void small_kernel(Src src, long long n, Glob
 }
 
 // The streaming accumulator's own kernels (one wavefront each).
+// Short sums (n <= kTinyMax) on one wavefront: no workgroup barrier, no
+// cross-wave sum and no merge, and the first batch of loads is in flight
+// while the accumulator is cleared.  A short sum is all fixed cost (Small:
+// the small superaccumulator's per-call overhead), so the kernel keeps only
+// what one wave needs: the small-superaccumulator body with 8 interleaved
+// copies, then the finisher.
+constexpr long long kTinyMax = 4096;
+constexpr int kTinyCopies = 8;
+template <class Src, class Fin>
+__global__ __launch_bounds__(64) void tiny_kernel(Src src, long long n, Fin fin) {
+  __shared__ long long acc[small_acc_words<kTinyCopies>()];
+  __shared__ unsigned long long spec[4];
+  const int lane = threadIdx.x;
+  // `direct`: below 1024 terms the copies' sum stays below 2^62 without
+  // carry steps, which the rounding accepts; the streaming finisher adds
+  // the total to a state and carries it itself
+  small_wave_accumulate<kTinyCopies, Src, true>(acc, spec, src, 0, n, lane, true);
+  __builtin_amdgcn_wave_barrier();
+  fin(acc, spec);
+}
+
 __global__ __launch_bounds__(64) void acc_zero_kernel(GlobalAcc *acc) {
   unsigned long long *w = reinterpret_cast<unsigned long long *>(acc);
   for (int i = threadIdx.x; i < (int)(sizeof(GlobalAcc) / 8); i += 64) w[i] = 0ull;
@@ -305,11 +326,20 @@ int large_variants(int32_t *out, int64_t cap) {
   return k;
 }
 
-hipError_t launch_small(const double *x, int64_t n, GlobalAcc *M, double *out, hipStream_t s, int grid) {
+// The small-only kernel, or for a short sum on one workgroup the one-wave
+// kernel.
+template <class Src, class Fin>
+hipError_t launch_small_any(const Src &src, int64_t n, const Fin &fin, GlobalAcc *M, hipStream_t s, int grid) {
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL((small_kernel<256, SrcF64, FinF64>), dim3(grid), dim3(256), 0, s, SrcF64{x}, (long long)n, M,
-                     FinF64{out});
+  if (grid == 1 && n <= kTinyMax)
+    hipLaunchKernelGGL((tiny_kernel<Src, Fin>), dim3(1), dim3(64), 0, s, src, (long long)n, fin);
+  else
+    hipLaunchKernelGGL((small_kernel<256, Src, Fin>), dim3(grid), dim3(256), 0, s, src, (long long)n, M, fin);
   return hipGetLastError();
+}
+
+hipError_t launch_small(const double *x, int64_t n, GlobalAcc *M, double *out, hipStream_t s, int grid) {
+  return launch_small_any(SrcF64{x}, n, FinF64{out}, M, s, grid);
 }
 
 // Other sources and finishers: the small kernel, or the large kernel in its
@@ -321,7 +351,7 @@ hipError_t launch_op(const Src &src, int64_t n, const Fin &fin, GlobalAcc *M, hi
                      int precombine) {
   if (grid < 1) grid = 1;
   if (small)
-    hipLaunchKernelGGL((small_kernel<256, Src, Fin>), dim3(grid), dim3(256), 0, s, src, (long long)n, M, fin);
+    return launch_small_any(src, n, fin, M, s, grid);
   else
     hipLaunchKernelGGL((large_kernel<BLOCK, VEC, 2, kCarryMode, Src, Fin>), dim3(grid), dim3(BLOCK), 0, s, src,
                        (long long)n, M, fin, precombine);
@@ -368,22 +398,14 @@ hipError_t launch_narrow(const T &src, int64_t n, float *out, GlobalAcc *M, hipS
 hipError_t launch_f32(const float *x, int64_t n, float *out, GlobalAcc *M, hipStream_t s, int grid, bool small,
                       int) {
   if (grid < 1) grid = 1;
-  if (small) {
-    hipLaunchKernelGGL((small_kernel<256, SrcF32, FinF32>), dim3(grid), dim3(256), 0, s, SrcF32{x}, (long long)n, M,
-                       FinF32{out});
-    return hipGetLastError();
-  }
+  if (small) return launch_small_any(SrcF32{x}, n, FinF32{out}, M, s, grid);
   return launch_narrow(NarrowSumF32{x}, n, out, M, s, grid);
 }
 
 hipError_t launch_dot_f32(const float *x, const float *y, int64_t n, float *out, GlobalAcc *M, hipStream_t s,
                           int grid, bool small, int) {
   if (grid < 1) grid = 1;
-  if (small) {
-    hipLaunchKernelGGL((small_kernel<256, SrcDotF32, FinF32>), dim3(grid), dim3(256), 0, s, SrcDotF32{x, y},
-                       (long long)n, M, FinF32{out});
-    return hipGetLastError();
-  }
+  if (small) return launch_small_any(SrcDotF32{x, y}, n, FinF32{out}, M, s, grid);
   if (((reinterpret_cast<uintptr_t>(x) ^ reinterpret_cast<uintptr_t>(y)) & 15) == 0)
     return launch_narrow(NarrowDotF32<true>{x, y}, n, out, M, s, grid);
   return launch_narrow(NarrowDotF32<false>{x, y}, n, out, M, s, grid);

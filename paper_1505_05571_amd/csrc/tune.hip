@@ -92,9 +92,11 @@ std::string config_json(const exsum_config &c) {
   std::snprintf(buf, sizeof buf,
                 "{\"large_block\": %d, \"large_vec\": %d, \"large_depth\": %d, \"large_mode\": %d, "
                 "\"large_grid\": %d, \"precombine\": %d, \"small_max\": %lld, \"small_grid\": %d, "
-                "\"seg_grid\": %d, \"seg_small_max\": %lld}",
+                "\"seg_grid\": %d, \"seg_small_max\": %lld, \"seg_mode\": %d, \"seg_block\": %d, "
+                "\"seg_group\": %d}",
                 c.large_block, c.large_vec, c.large_depth, c.large_mode, c.large_grid, c.precombine,
-                (long long)c.small_max, c.small_grid, c.seg_grid, (long long)c.seg_small_max);
+                (long long)c.small_max, c.small_grid, c.seg_grid, (long long)c.seg_small_max, c.seg_mode,
+                c.seg_block, c.seg_group);
   return buf;
 }
 
@@ -423,10 +425,12 @@ extern "C" int exsum_load_tuning(const char *cache_path) {
   const size_t cpos = t.find("\"config\":");
   if (cpos == std::string::npos) return EXSUM_EINVAL;
   exsum_config c;
-  long long v[10];
-  const char *keys[10] = {"large_block", "large_vec",  "large_depth", "large_mode", "large_grid",
-                          "precombine",  "small_max",  "small_grid",  "seg_grid",   "seg_small_max"};
-  for (int i = 0; i < 10; i++)
+  (void)exsum_get_config(&c);
+  long long v[13];
+  const char *keys[13] = {"large_block", "large_vec",  "large_depth", "large_mode", "large_grid",
+                          "precombine",  "small_max",  "small_grid",  "seg_grid",   "seg_small_max",
+                          "seg_mode",    "seg_block",  "seg_group"};
+  for (int i = 0; i < 13; i++)
     if (!json_int(t, keys[i], &v[i], cpos)) return EXSUM_EINVAL;
   c.large_block = (int32_t)v[0];
   c.large_vec = (int32_t)v[1];
@@ -438,6 +442,10 @@ extern "C" int exsum_load_tuning(const char *cache_path) {
   c.small_grid = (int32_t)v[7];
   c.seg_grid = (int32_t)v[8];
   c.seg_small_max = v[9];
+  c.seg_mode = (int32_t)v[10];
+  c.seg_block = (int32_t)v[11];
+  c.seg_group = (int32_t)v[12];
+  c.seg_pad = 0;
   DeviceId id;
   const int st = device_id(&id);
   if (st != EXSUM_OK) return st;

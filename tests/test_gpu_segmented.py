@@ -47,11 +47,19 @@ def seg_bits(ex, xt, offt, **kw):
 
 VARIANTS = [
     dict(),
-    dict(seg_small_max=0),
-    dict(seg_small_max=65536, seg_grid=37),
-    dict(seg_small_max=100, seg_grid=5),
-    dict(seg_small_max=2048, seg_grid=1),
-    dict(seg_small_max=4096, seg_grid=1000),
+    dict(seg_mode=0),
+    dict(seg_mode=0, seg_small_max=0),
+    dict(seg_mode=0, seg_small_max=65536, seg_grid=37),
+    dict(seg_mode=0, seg_small_max=100, seg_grid=5),
+    dict(seg_mode=0, seg_small_max=2048, seg_grid=1),
+    dict(seg_mode=0, seg_small_max=4096, seg_grid=1000),
+    # one persistent launch: every workgroup shape, unit size and grid
+    dict(seg_mode=1),
+    dict(seg_mode=1, seg_block=256),
+    dict(seg_mode=1, seg_block=1024, seg_group=64, seg_small_max=100),
+    dict(seg_mode=1, seg_block=512, seg_grid=1, seg_group=1),
+    dict(seg_mode=1, seg_block=256, seg_grid=37, seg_small_max=65536, seg_group=7),
+    dict(seg_mode=1, seg_small_max=0, seg_grid=1000),
 ]
 
 
@@ -117,16 +125,18 @@ def test_long_carry_chain_segments(ex):
         assert np.array_equal(seg_bits(ex, xt, offt, **v), want), v
 
 
-def test_repeated_calls_and_shrinking_batches(ex):
+@pytest.mark.parametrize("mode", [0, 1])
+def test_repeated_calls_and_shrinking_batches(ex, mode):
     x, off = W.segments(nseg=5000, seed=5, hi=100000)
     xt = dev(x)
     for nseg in (5000, 17, 4999, 1):
         o = off[:nseg + 1]
         want = oracle.segmented_f64(x, o)
-        assert np.array_equal(seg_bits(ex, xt, dev(o)), want), nseg
+        assert np.array_equal(seg_bits(ex, xt, dev(o), seg_mode=mode), want), nseg
 
 
-def test_fewer_terms_than_workgroups(ex):
+@pytest.mark.parametrize("mode", [0, 1])
+def test_fewer_terms_than_workgroups(ex, mode):
     # the kernel caps its grid at the number of terms; a segment cut into
     # pieces must count exactly the workgroups that hold one
     x = W.uniform_exponent(300, seed=11)
@@ -135,16 +145,20 @@ def test_fewer_terms_than_workgroups(ex):
         want = oracle.segmented_f64(x, o)
         xt, offt = dev(x), dev(o)
         for grid in (0, 1, 2, 200, 1000, 8192):
-            assert np.array_equal(seg_bits(ex, xt, offt, seg_grid=grid), want), (off, grid)
-            assert np.array_equal(seg_bits(ex, xt, offt, seg_grid=grid, seg_small_max=0), want), (off, grid)
+            assert np.array_equal(seg_bits(ex, xt, offt, seg_grid=grid, seg_mode=mode), want), (off, grid)
+            assert np.array_equal(seg_bits(ex, xt, offt, seg_grid=grid, seg_small_max=0, seg_mode=mode),
+                                  want), (off, grid)
 
 
 def test_full_size_batched_workload(ex):
-    # 65536 segments, lognormal lengths (median 1000, sigma 2), default config
+    # 65536 segments, lognormal lengths (median 1000, sigma 2), both launch
+    # modes, default shapes and every persistent workgroup size
     x, off = W.segments(nseg=65536, seed=0)
     want = oracle.segmented_f64(x, off)
-    got = seg_bits(ex, dev(x), dev(off))
-    assert np.array_equal(got, want)
+    xt, offt = dev(x), dev(off)
+    for kw in (dict(), dict(seg_mode=0), dict(seg_mode=1, seg_block=256), dict(seg_mode=1, seg_block=512),
+               dict(seg_mode=1, seg_block=1024)):
+        assert np.array_equal(seg_bits(ex, xt, offt, **kw), want), kw
 
 
 def test_full_size_batched_workload_sigma_163(ex):
@@ -154,8 +168,9 @@ def test_full_size_batched_workload_sigma_163(ex):
     want = oracle.segmented_f64(x, off)
     xt, offt = dev(x), dev(off)
     assert np.array_equal(seg_bits(ex, xt, offt), want)
-    for sm in (0, 4096, 65536, 1 << 20):
-        assert np.array_equal(seg_bits(ex, xt, offt, seg_small_max=sm), want), sm
+    for mode in (0, 1):
+        for sm in (0, 4096, 65536, 1 << 20):
+            assert np.array_equal(seg_bits(ex, xt, offt, seg_small_max=sm, seg_mode=mode), want), (mode, sm)
 
 
 def test_many_segments_count_partition(ex):
@@ -166,6 +181,7 @@ def test_many_segments_count_partition(ex):
     xt, offt = dev(x), dev(off)
     assert np.array_equal(seg_bits(ex, xt, offt), want)
     assert np.array_equal(seg_bits(ex, xt, offt, seg_small_max=64), want)
+    assert np.array_equal(seg_bits(ex, xt, offt, seg_mode=1 - DEFAULT[0].seg_mode), want)
     # a slice below the threshold takes the weight partition
     sub = off[:200001] - off[0]
     assert np.array_equal(seg_bits(ex, dev(x[:int(sub[-1])]), dev(sub)), want[:200000])

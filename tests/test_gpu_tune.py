@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 FIELDS = ("large_block", "large_vec", "large_depth", "large_mode", "large_grid", "precombine", "small_max",
-          "small_grid", "seg_grid", "seg_small_max")
+          "small_grid", "seg_grid", "seg_small_max", "seg_mode", "seg_block", "seg_group")
 
 
 @pytest.fixture(scope="module")
