@@ -180,6 +180,14 @@ def copy_reference(torch, dev, x, args):
                       "read_plus_write_GBs": round(16.0 * x.size / t / 1e9, 1)}), flush=True)
 
 
+def server_config_info(ex, args):
+    c = ex.exsum_server_default_config()
+    for item in filter(None, args.serve_config.split(",")):
+        k, v = item.split("=")
+        setattr(c, k.strip(), int(v))
+    return c.as_dict()
+
+
 def serve_bench(args):
     """Continuous-batching server against serial exsum_f64 calls on one
     trace, replayed in real time at two loads."""
@@ -219,11 +227,15 @@ def serve_bench(args):
 
     loads = {}
     served_ok = True
-    for rho in (0.8, 2.0):
+    for rho in [float(r) for r in args.serve_loads.split(",")]:
         arrival = np.cumsum(gaps) * (mean_service / rho)
         arrival -= arrival[0]
         out_b = torch.full((nreq,), np.nan, dtype=torch.float64, device=dev)
-        with ex.Server(stream=torch.cuda.current_stream()) as srv:
+        scfg = ex.exsum_server_default_config()
+        for item in filter(None, args.serve_config.split(",")):
+            k, v = item.split("=")
+            setattr(scfg, k.strip(), int(v))
+        with ex.Server(scfg, stream=torch.cuda.current_stream()) as srv:
             lat_b, mk_b = srv.replay(pt, starts, lens, arrival, out_b)
         served_ok &= bool(np.array_equal(out_b.cpu().numpy().view(np.uint64), ref))
         out_s = torch.full((nreq,), np.nan, dtype=torch.float64, device=dev)
@@ -231,13 +243,14 @@ def serve_bench(args):
         served_ok &= bool(np.array_equal(out_s.cpu().numpy().view(np.uint64), ref))
         loads["rho_%g" % rho] = {"batched": summary(lat_b, mk_b), "serial": summary(lat_s, mk_s)}
         print(json.dumps({"progress": "rho %g done" % rho}), file=sys.stderr, flush=True)
-    head = loads["rho_0.8"]["batched"]
+    head = loads["rho_%g" % float(args.serve_loads.split(",")[0])]["batched"]
     result = {
         "metric": "served exact sums: GB/s and p50/p99 request latency (0-ulp)",
         "value": head["GBs"], "unit": "GB/s", "n_gpus": 1, "steps": nreq, "warmup": 20,
         "ms_per_step": round(head["makespan_s"] * 1e3 / nreq, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": {"workload": WORKLOADS["serve"], "tuning": tuning_info(), "requests": nreq, "terms": int(lens.sum()),
+                   "server": server_config_info(ex, args),
                    "mean_serial_service_ms": round(mean_service * 1e3, 4)},
         "loads": loads,
         "parity": {"batched_and_serial_equal": served_ok, "oracle_checked_requests": int(nreq),
@@ -357,6 +370,10 @@ def main():
     ap.add_argument("--workload", default="uniform_exponent", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=20000)
+    ap.add_argument("--serve-config", default="",
+                    help="server configuration fields for the serve workload, e.g. max_inflight=8")
+    ap.add_argument("--serve-loads", default="0.8,2",
+                    help="offered loads (multiples of the serial service rate) the serve workload replays")
     ap.add_argument("--autotune", action="store_true",
                     help="run the library's configuration tuner before the workload (untimed)")
     ap.add_argument("--config", default="",

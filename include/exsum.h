@@ -212,13 +212,14 @@ typedef struct {
  * timing candidates on synthetic inputs (10^8 terms of three exponent
  * distributions for the large-kernel variant, scored by the worst ratio to
  * the fastest candidate; lengths 512 .. 65536 for the small/large crossover;
- * a batch of 16384 lognormal segments for seg_small_max), and make the
- * chosen configuration the process configuration.  Every candidate's result
- * bits are compared with the others'; a difference (a defect: configurations
- * change only speed) returns EXSUM_EDEVICE.  Takes a few seconds and 1.6 GB
- * of device memory,
- * allocated and freed inside the call; synchronises `stream`.  On any error
- * the previous configuration stays in force.
+ * two batches of 32768 lognormal segments, sigma 2 and 1.63, for the
+ * segmented launch: mode, seg_small_max, seg_grid, seg_block and seg_group,
+ * again scored by the worst ratio), and make the chosen configuration the
+ * process configuration.  Every candidate's result bits are compared with
+ * the others'; a difference (a defect: configurations change only speed)
+ * returns EXSUM_EDEVICE.  Takes a few seconds and about 2.7 GB of device
+ * memory, allocated and freed inside the call; synchronises `stream`.  On
+ * any error the previous configuration stays in force.
  *   cache_path : if not NULL, the result is also written there as JSON
  *                (device name, architecture, compute units, configuration,
  *                the measured times), for exsum_load_tuning().

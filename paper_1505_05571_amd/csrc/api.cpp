@@ -57,7 +57,7 @@ exsum_config default_config() {
   c.seg_small_max = 12288;
   c.seg_mode = 0;
   c.seg_block = 256;
-  c.seg_group = 16;
+  c.seg_group = 8;
   c.seg_pad = 0;
   return c;
 }
@@ -175,6 +175,7 @@ int op_setup(hipStream_t s, exsum_config *c, Workspace **w, int *dev) {
 bool acc_ptr_ok(const void *acc) { return acc != nullptr && (reinterpret_cast<uintptr_t>(acc) & 63) == 0; }
 
 }  // namespace
+
 }  // namespace exsum
 
 using namespace exsum;

@@ -387,11 +387,12 @@ __global__ __launch_bounds__(BLOCK) void seg_short_kernel(const double *__restri
 // long segments of its term range (long_phase, as above); then every wave,
 // on its own, claims units of short segments until none are left.  A unit is
 // (class c, group g): the segments [g*group, (g+1)*group) whose length falls
-// in class c (at least 4096 terms, or fewer; at most small_max).  The groups are dealt to kCursors cursors, group g to cursor
-// g mod kCursors, and each cursor hands out all its units of the longer
-// class first: the longest short segments start first and the last units
-// handed out hold only shorter ones, so no compute unit waits long for
-// another at the end, and a workgroup whose term range held few
+// in class c (at least 4096 terms, at least 512, the rest; at most
+// small_max).  The groups are dealt to kCursors cursors, group g to cursor
+// g mod kCursors, and each cursor hands out all its class-A units, then its
+// class-B ones, then class C: the longest short segments start first and
+// the last units handed out are the shortest, so no compute unit waits long
+// for another at the end, and a workgroup whose term range held few
 // long-segment terms goes on to short ones at once.  A wave claims from the
 // cursor of its own XCD (workgroups are dealt to the eight XCDs in turn)
 // and, once that is exhausted, from the others, so the claims spread over
@@ -410,10 +411,9 @@ __global__ __launch_bounds__(BLOCK) void seg_short_kernel(const double *__restri
 // another wave or workgroup.
 // ---------------------------------------------------------------------------
 constexpr int kCursors = 8;
-// Length classes of the cursors' order: segments of at least kClassA terms,
-// then all shorter ones together (handing out the shortest ones last, on
-// their own, left every wave on latency-bound tiny sums at the end).
-constexpr int kUnitClasses = 2;
+// Length classes of the cursors' order: at least kClassA terms, at least
+// kClassB, the rest (two classes, the shorter ones together, measured slower).
+constexpr int kUnitClasses = 3;
 struct SegCtl {
   unsigned int cursor[kCursors][32];    // one 128-byte line each
   unsigned int done;                    // waves that have made their last claim
@@ -489,7 +489,7 @@ __device__ __forceinline__ void unit_run(const SegUnit &u, const SrcF64 &src, do
                                          long long small_max, long long *acc, unsigned long long *spec, int lane,
                                          const Hook &before_last) {
   const long long len = u.s1 - u.s0;
-  const long long c = len >= kClassA ? 0 : 1;
+  const long long c = len >= kClassA ? 0 : (len >= kClassB ? 1 : 2);
   unsigned long long m = __ballot(u.have && len <= small_max && c == u.cls);
   if (m == 0ull) before_last();
   for (; m; m &= m - 1) {

@@ -4,14 +4,15 @@
 // A piece is a range of one request's terms.  Pieces [0, nshort) are short
 // and each is summed by one wavefront with the small-superaccumulator body;
 // the others are summed one per workgroup with the large accumulator in
-// carry mode.  A request made of one piece is rounded where it is summed.  A
-// request cut into several pieces (possibly over several steps) adds each
-// piece into its accumulator slot with 64-bit atomics and takes a ticket;
-// pieces of the step that completes the request carry the total piece count,
-// and the piece whose ticket completes the count rounds (Discussion: add the
-// small superaccumulators of the parts, round once).  Steps run in stream
-// order, so every piece of an earlier step has been added before any piece
-// of a later one.
+// carry mode (a step of short pieces only runs a lighter kernel of
+// one-wavefront workgroups).  A request made of one piece is rounded where
+// it is summed.  A request cut into several pieces (possibly over several
+// steps) adds each piece into its accumulator slot with 64-bit atomics and
+// takes a ticket; pieces of the step that completes the request carry the
+// total piece count, and the piece whose ticket completes the count rounds
+// (Discussion: add the small superaccumulators of the parts, round once).
+// Steps run in stream order, so every piece of an earlier step has been
+// added before any piece of a later one.
 #include "exsum_blocks.h"
 #include "exsum_internal.h"
 
@@ -77,7 +78,26 @@ __global__ __launch_bounds__(BLOCK) void piece_kernel(const Table P, int nshort,
   }
 }
 
+// A step whose pieces are all short (the common case at light load): one
+// wavefront per workgroup and per piece, with only that wave's small
+// accumulator in LDS, so a step of one short request costs what a single
+// short sum costs.  The accumulator is cleared under the first loads of each
+// piece.
+template <class Table>
+__global__ __launch_bounds__(64) void piece_short_kernel(const Table P, int nshort, GlobalAcc *__restrict__ slots) {
+  __shared__ long long acc[small_acc_words<kPieceCopies>()];
+  __shared__ unsigned long long spec[4];
+  const int lane = threadIdx.x;
+  for (int p = (int)blockIdx.x; p < nshort; p += (int)gridDim.x) {
+    const Piece pc = P[p];
+    small_wave_accumulate<kPieceCopies, SrcF64, true>(acc, spec, SrcF64{pc.x}, 0, pc.n, lane, pc.expected == 1u);
+    GlobalAcc *g = pc.expected == 1u ? nullptr : &slots[pc.slot];
+    wave_merge_and_round(acc, spec, g, pc.expected, pc.out, lane);
+  }
+}
+
 constexpr int kPieceBlock = 512;
+constexpr int kShortStepGrid = 4096;     // workgroups of the short-only step kernel at most
 
 }  // namespace
 
@@ -85,6 +105,18 @@ hipError_t launch_pieces(const Piece *pieces, const Piece *host_pieces, int nsho
                          hipStream_t s, int grid, int precombine) {
   if (npieces <= 0) return hipSuccess;
   if (grid < 1) grid = 1;
+  if (nshort == npieces) {
+    const int g = npieces < kShortStepGrid ? npieces : kShortStepGrid;
+    if (host_pieces != nullptr && npieces <= kInlinePieces) {
+      InlinePieces t;
+      for (int i = 0; i < kInlinePieces; i++) t.p[i] = i < npieces ? host_pieces[i] : Piece{nullptr, 0, nullptr, 0, 0u};
+      hipLaunchKernelGGL((piece_short_kernel<InlinePieces>), dim3(g), dim3(64), 0, s, t, nshort, slots);
+    } else {
+      hipLaunchKernelGGL((piece_short_kernel<PieceTable>), dim3(g), dim3(64), 0, s, PieceTable{pieces}, nshort,
+                         slots);
+    }
+    return hipGetLastError();
+  }
   if (host_pieces != nullptr && npieces <= kInlinePieces) {
     InlinePieces t;
     for (int i = 0; i < kInlinePieces; i++) t.p[i] = i < npieces ? host_pieces[i] : Piece{nullptr, 0, nullptr, 0, 0u};

@@ -10,8 +10,11 @@
 //      by its worst ratio to the fastest candidate;
 //   2. small_max: the largest tested length at which the small-only kernel
 //      still beats the large one;
-//   3. seg_small_max: the short/long threshold of segmented calls, on a batch
-//      of lognormal segment lengths.
+//   3. the segmented call's launch: mode (two launches or one persistent
+//      launch), threshold seg_small_max, workgroups, and for the persistent
+//      launch its workgroup size and unit size, timed on two batches of
+//      lognormal segment lengths (sigma 2 and 1.63, median 1000) and chosen
+//      by the worst ratio to the fastest candidate.
 // The result becomes the process configuration and can be written to a
 // JSON file that exsum_load_tuning() reads back on the same kind of device.
 #include <hip/hip_runtime.h>
@@ -84,8 +87,14 @@ struct Timer {
 struct Variant {
   int block, vec, depth, mode;
 };
-const Variant kVariants[] = {{256, 6, 3, 0}, {256, 4, 3, 0}, {256, 2, 4, 0}, {512, 3, 2, 0}, {512, 2, 2, 0},
-                             {256, 4, 3, 1}, {512, 4, 2, 1}, {512, 2, 4, 1}, {1024, 2, 2, 1}, {1024, 4, 2, 1}};
+// The large kernel's built shapes, from the library's one table.
+std::vector<Variant> built_variants() {
+  std::vector<int32_t> v(4 * (size_t)large_variants(nullptr, 0));
+  const int n = large_variants(v.data(), (int64_t)(v.size() / 4));
+  std::vector<Variant> out;
+  for (int k = 0; k < n; k++) out.push_back(Variant{v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]});
+  return out;
+}
 
 std::string config_json(const exsum_config &c) {
   char buf[512];
@@ -161,11 +170,11 @@ int device_id(DeviceId *d, std::string *why = nullptr) {
   return status_of(e);
 }
 
-// Lognormal segment lengths (median 1000, sigma 2, clipped to [1, 1e6]) as
-// offsets; deterministic for a seed.
-std::vector<int64_t> lognormal_offsets(int nseg, unsigned seed) {
+// Lognormal segment lengths (median 1000, clipped to [1, 1e6]) as offsets;
+// deterministic for a seed.
+std::vector<int64_t> lognormal_offsets(int nseg, unsigned seed, double sigma) {
   std::mt19937_64 g(seed);
-  std::normal_distribution<double> nd(std::log(1000.0), 2.0);
+  std::normal_distribution<double> nd(std::log(1000.0), sigma);
   std::vector<int64_t> off(nseg + 1, 0);
   for (int i = 0; i < nseg; i++) {
     double L = std::rint(std::exp(nd(g)));
@@ -232,17 +241,18 @@ int autotune_body(const char *cache_path, std::string &js, std::string &err, voi
 
   // inputs: 10^8 terms (800 MB, beyond the last-level cache; not a power of
   // two, so workgroup ranges do not all start on the same address bits) for
-  // the single sums; a 16384-segment batch
+  // the single sums; two batches of 32768 segments with lognormal lengths,
+  // sigma 2 and 1.63 (the benchmark batches' shapes at half their count)
   const int64_t n_single = 100000000;
-  const int nseg = 16384;
-  const std::vector<int64_t> off = lognormal_offsets(nseg, 12345u);
-  const int64_t n_seg = off[nseg];
+  const int nseg = 32768;
+  const std::vector<int64_t> offs[2] = {lognormal_offsets(nseg, 12345u, 2.0), lognormal_offsets(nseg, 54321u, 1.63)};
+  const int64_t n_seg = std::max(offs[0][nseg], offs[1][nseg]);
   const int64_t n_buf = std::max(n_single, n_seg);
   Buffers B;
   hipError_t e = hipMalloc(&B.x, sizeof(double) * n_buf);
   if (e == hipSuccess) e = hipMalloc(&B.x2, sizeof(double) * n_single);
   if (e == hipSuccess) e = hipMalloc(&B.out, sizeof(double) * (nseg + 64));
-  if (e == hipSuccess) e = hipMalloc(&B.off, sizeof(int64_t) * (nseg + 1));
+  if (e == hipSuccess) e = hipMalloc(&B.off, sizeof(int64_t) * 2 * (nseg + 1));
   if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? EXSUM_ENOMEM : status_of(e), "allocating the inputs");
   Timer T(s);
   std::string log;
@@ -264,7 +274,7 @@ int autotune_body(const char *cache_path, std::string &js, std::string &err, voi
   const int pcs[] = {0, 8, 16, 32};
   std::vector<unsigned long long> want, got;
   std::vector<exsum_config> cands;
-  for (const Variant &v : kVariants)
+  for (const Variant &v : built_variants())
     for (int g : grids)
       for (int pc : pcs) {
         exsum_config c = base;
@@ -363,34 +373,70 @@ int autotune_body(const char *cache_path, std::string &js, std::string &err, voi
     best.small_max = chosen;
   }
 
-  // 3. segmented short/long threshold
+  // 3. segmented launch: candidates over the mode, the short/long threshold,
+  // the workgroups and the persistent launch's shapes; each timed on both
+  // batches (best of two rounds), scored by its worst ratio to the fastest
+  // on either, and every candidate's bits compared with the first's
   {
-    e = hipMemcpyAsync(B.off, off.data(), sizeof(int64_t) * (nseg + 1), hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return fail(status_of(e), "copying the offsets");
+    for (int b = 0; b < 2; b++) {
+      e = hipMemcpyAsync(B.off + b * (nseg + 1), offs[b].data(), sizeof(int64_t) * (nseg + 1),
+                         hipMemcpyHostToDevice, s);
+      if (e != hipSuccess) return fail(status_of(e), "copying the offsets");
+    }
     if ((st = gen(n_seg, 2, 13)) != EXSUM_OK) return fail(st, "generating an input");
-    const int64_t sms[] = {4096, 8192, 12288, 16384, 32768, 65536};
-    double bt = 1e300;
-    int64_t bsm = best.seg_small_max;
-    std::vector<unsigned long long> ref;
-    log += "\"seg_small_max\": [";
-    for (size_t k = 0; k < sizeof sms / sizeof sms[0]; k++) {
-      exsum_config c = best;
-      c.seg_small_max = sms[k];
-      if ((st = exsum_set_config(&c)) != EXSUM_OK) return fail(st, "setting a candidate configuration");
-      const double t = T.time_us([&] { return exsum_segmented_f64(B.x, B.off, nseg, B.out, s); }, 5);
-      if (t < 0) return fail(EXSUM_EDEVICE, "a timed call failed");
-      if ((st = bits_of(nseg, &got)) != EXSUM_OK) return fail(st, "reading a result");
-      if (k == 0) ref = got;
-      if (got != ref) return fail(EXSUM_EDEVICE, "seg_small_max " + std::to_string(sms[k]) + " changed the bits");
-      std::snprintf(line, sizeof line, "%s[%lld, %.2f]", k ? ", " : "", (long long)sms[k], t);
-      log += line;
-      if (t < bt) {
-        bt = t;
-        bsm = sms[k];
+    std::vector<exsum_config> sc;
+    for (int64_t sm : {8192, 12288, 16384})
+      for (int g : {0, 3 * id.cus}) {
+        exsum_config c = best;
+        c.seg_mode = 0;
+        c.seg_small_max = sm;
+        c.seg_grid = g;
+        sc.push_back(c);
       }
+    for (int blk : {256, 512})
+      for (int grp : {8, 16})
+        for (int64_t sm : {8192, 12288}) {
+          exsum_config c = best;
+          c.seg_mode = 1;
+          c.seg_block = blk;
+          c.seg_group = grp;
+          c.seg_small_max = sm;
+          c.seg_grid = 0;
+          sc.push_back(c);
+        }
+    std::vector<double> ts[2];
+    std::vector<unsigned long long> ref[2];
+    for (int b = 0; b < 2; b++) ts[b].assign(sc.size(), 1e300);
+    for (int round = 0; round < 2; round++)
+      for (int b = 0; b < 2; b++)
+        for (size_t i = 0; i < sc.size(); i++) {
+          if ((st = exsum_set_config(&sc[i])) != EXSUM_OK) return fail(st, "setting a candidate configuration");
+          const int64_t *o = B.off + b * (nseg + 1);
+          const double t = T.time_us([&] { return exsum_segmented_f64(B.x, o, nseg, B.out, s); }, 5);
+          if (t < 0) return fail(EXSUM_EDEVICE, "a timed call failed (segmented)");
+          if ((st = bits_of(nseg, &got)) != EXSUM_OK) return fail(st, "reading a result");
+          if (ref[b].empty()) ref[b] = got;
+          if (got != ref[b]) return fail(EXSUM_EDEVICE, "segmented candidate " + config_json(sc[i]) + " changed the bits");
+          ts[b][i] = std::min(ts[b][i], t);
+        }
+    const double m0 = *std::min_element(ts[0].begin(), ts[0].end());
+    const double m1 = *std::min_element(ts[1].begin(), ts[1].end());
+    size_t bi = 0;
+    std::vector<double> sscore(sc.size());
+    for (size_t i = 0; i < sc.size(); i++) {
+      sscore[i] = std::max(ts[0][i] / m0, ts[1][i] / m1);
+      if (sscore[i] < sscore[bi]) bi = i;
+    }
+    log += "\"segmented\": [";
+    for (size_t i = 0; i < sc.size(); i++) {
+      std::snprintf(line, sizeof line, "%s{\"mode\": %d, \"small_max\": %lld, \"grid\": %d, \"block\": %d, "
+                    "\"group\": %d, \"us\": [%.2f, %.2f], \"score\": %.4f}", i ? ", " : "", sc[i].seg_mode,
+                    (long long)sc[i].seg_small_max, sc[i].seg_grid, sc[i].seg_block, sc[i].seg_group, ts[0][i],
+                    ts[1][i], sscore[i]);
+      log += line;
     }
     log += "]";
-    best.seg_small_max = bsm;
+    best = sc[bi];
   }
   if ((st = exsum_set_config(&best)) != EXSUM_OK) return fail(st, "setting a candidate configuration");
   restore.keep = true;

@@ -40,6 +40,15 @@ def test_autotune_and_cache(ex, tmp_path):
     assert as_dict(ex.exsum_get_config()) == rep["config"]
     assert json.loads(open(path).read())["config"] == rep["config"]
     assert rep["cus"] > 0 and "gfx" in rep["arch"]
+    # the segmented launch was chosen among both modes on both batch shapes
+    seg = rep["measured"]["segmented"]
+    assert {r["mode"] for r in seg} == {0, 1} and all(len(r["us"]) == 2 for r in seg)
+    best = min(seg, key=lambda r: r["score"])
+    assert best["score"] >= 1.0
+    cfg = rep["config"]
+    assert (cfg["seg_mode"], cfg["seg_small_max"], cfg["seg_grid"]) == (best["mode"], best["small_max"], best["grid"])
+    if best["mode"] == 1:
+        assert (cfg["seg_block"], cfg["seg_group"]) == (best["block"], best["group"])
     # back to the defaults, then the cache restores the tuned configuration
     ex.exsum_set_config(base)
     ex.exsum_load_tuning(path)
@@ -50,6 +59,10 @@ def test_autotune_and_cache(ex, tmp_path):
         out = ex.exsum_f64(torch.from_numpy(x).to("cuda:0"))
         assert int(out.cpu().numpy().view(np.uint64)[0]) == int(oracle.sum_f64(x)), n
     xs, off = W.segments(nseg=4000, seed=3, hi=200000)
+    got = ex.exsum_segmented_f64(torch.from_numpy(xs).to("cuda:0"), torch.from_numpy(off).to("cuda:0"))
+    assert np.array_equal(got.cpu().numpy().view(np.uint64), oracle.segmented_f64(xs, off))
+    # the full sigma 1.63 batch under the tuned segmented configuration
+    xs, off = W.segments(nseg=65536, seed=0, sigma=1.63)
     got = ex.exsum_segmented_f64(torch.from_numpy(xs).to("cuda:0"), torch.from_numpy(off).to("cuda:0"))
     assert np.array_equal(got.cpu().numpy().view(np.uint64), oracle.segmented_f64(xs, off))
     # a cache from another kind of device is refused and changes nothing
