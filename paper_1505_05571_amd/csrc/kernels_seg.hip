@@ -341,42 +341,17 @@ __global__ __launch_bounds__(BLOCK) void seg_short_kernel(const double *__restri
     }
     total = __builtin_amdgcn_readfirstlane(total);
     __syncthreads();
-    // Claim the next entry of the round.  Every lane adds 1, so one claim
-    // advances the counter by 64 and the first lane's old value
-    // (wave-uniform) names the claimed entry; no value of one lane is
-    // broadcast, and every loop and branch below stays scalar.
-    auto claim = [&](int &j, long long &a, long long &b) -> bool {
+    for (;;) {
+      // every lane adds 1, so one claim advances the counter by 64 and the
+      // first lane's old value (wave-uniform) names the claimed entry; no
+      // value of one lane is broadcast, and the loop stays scalar
       const int k = __builtin_amdgcn_readfirstlane(atomicAdd(&S.cnt, 1)) >> 6;
-      if (k >= total) return false;
-      j = __builtin_amdgcn_readfirstlane(S.ord[k]);
-      a = uniform_i64(S.lo[j]);
-      b = uniform_i64(S.hi[j]);
-      return true;
-    };
-    // A wave holds two segments: while it sums one, the first loads of the
-    // next are already in flight, so it never waits a full memory latency
-    // at a segment start.
-    const SrcF64 src{x};
-    int j0 = 0, j1 = 0;
-    long long a0 = 0, b0 = 0, a1 = 0, b1 = 0;
-    PairRange<SrcF64> R0, R1;
-    bool h0 = claim(j0, a0, b0);
-    if (h0 && b0 > a0) pair_range_begin(R0, src, a0, b0, lane);
-    small_wave_zero<kShortCopies>(acc, spec, lane);
-    while (h0) {
-      const bool h1 = claim(j1, a1, b1);
-      if (h1 && b1 > a1) pair_range_begin(R1, src, a1, b1, lane);
-      if (b0 > a0) pair_range_add<kShortCopies>(acc, spec, src, R0, lane);
-      small_wave_finish<kShortCopies>(acc, lane, b0 - a0 < 1024);
-      wave_merge_and_round(acc, spec, nullptr, 1u, &out[r0 + j0], lane);
-      small_wave_zero<kShortCopies>(acc, spec, lane);
-      if (!h1) break;
-      h0 = claim(j0, a0, b0);
-      if (h0 && b0 > a0) pair_range_begin(R0, src, a0, b0, lane);
-      if (b1 > a1) pair_range_add<kShortCopies>(acc, spec, src, R1, lane);
-      small_wave_finish<kShortCopies>(acc, lane, b1 - a1 < 1024);
-      wave_merge_and_round(acc, spec, nullptr, 1u, &out[r0 + j1], lane);
-      small_wave_zero<kShortCopies>(acc, spec, lane);
+      if (k >= total) break;
+      const int j = __builtin_amdgcn_readfirstlane(S.ord[k]);
+      const long long a = uniform_i64(S.lo[j]), b = uniform_i64(S.hi[j]);
+      // the accumulator is cleared under the segment's first loads
+      small_wave_accumulate<kShortCopies, SrcF64, true>(acc, spec, SrcF64{x}, a, b, lane, true);
+      wave_merge_and_round(acc, spec, nullptr, 1u, &out[r0 + j], lane);
     }
     __syncthreads();
   }
