@@ -104,3 +104,39 @@ def test_capture_binary32(ex):
         got = out.cpu().numpy().view(np.uint32)
         assert int(got[0]) == int(oracle.sum_f32(xv)), rep
         assert int(got[1]) == int(oracle.dot_f32(xv, y)), rep
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_capture_segmented_both_modes(ex, mode):
+    """The segmented call in either launch mode (two launches, or the
+    persistent launch whose device cursors its last wave resets) captured and
+    replayed several times, with eager segmented calls on another stream and
+    poisoned outputs between replays: every replay gives the oracle's bits."""
+    base = ex.exsum_get_config()
+    c = ex.exsum_get_config()
+    c.seg_mode = mode
+    ex.exsum_set_config(c)
+    try:
+        s = torch.cuda.Stream()
+        xs, off = W.segments(nseg=20000, seed=36, hi=100000)
+        want = oracle.segmented_f64(xs, off)
+        with torch.cuda.stream(s):
+            xst = torch.from_numpy(xs).to("cuda:0")
+            offt = torch.from_numpy(off).to("cuda:0")
+            outs = torch.empty(off.size - 1, dtype=torch.float64, device="cuda:0")
+            ex.exsum_segmented_f64(xst, offt, out=outs, stream=s, check=False)   # this stream's workspace
+        s.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            ex.exsum_segmented_f64(xst, offt, out=outs, stream=s, check=False)
+        other = torch.empty_like(outs)
+        for rep in range(4):
+            outs.fill_(float("nan"))
+            ex.exsum_segmented_f64(xst, offt, out=other, check=False)          # eager, current stream
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert np.array_equal(bits(outs), want), rep
+            assert np.array_equal(bits(other), want), rep
+    finally:
+        ex.exsum_set_config(base)
