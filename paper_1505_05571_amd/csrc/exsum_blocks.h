@@ -1144,19 +1144,23 @@ __device__ __forceinline__ void small_batch_load(typename Src::Raw (&b)[kSmallU]
 }
 // Add one lane's K terms (bit patterns; a 0 adds nothing).  A batch of
 // finite terms takes one branch-free path; only a batch holding an infinity
-// or NaN goes term by term.
+// or NaN (exponent field 2047) goes term by term.
 template <int K>
 __device__ __forceinline__ void small_terms_add(long long *mine, unsigned long long *spec,
                                                 const unsigned long long (&t)[K]) {
+  unsigned int e[K];
   bool special = false;
 #pragma unroll
-  for (int j = 0; j < K; j++) special |= is_special(t[j]);
+  for (int j = 0; j < K; j++) {
+    e[j] = term_exp(t[j]);
+    special |= e[j] == 2047u;
+  }
   if (!__any(special)) {
 #pragma unroll
     for (int j = 0; j < K; j++) {
       int h;
       long long plo, phi;
-      term_pieces(t[j], h, plo, phi);
+      term_pieces_e(t[j], e[j], h, plo, phi);
       atomicAdd((unsigned long long *)&mine[h], (unsigned long long)plo);
       atomicAdd((unsigned long long *)&mine[h + 1], (unsigned long long)phi);
     }
@@ -1169,7 +1173,7 @@ __device__ __forceinline__ void small_terms_add(long long *mine, unsigned long l
     } else {
       int h;
       long long plo, phi;
-      term_pieces(t[j], h, plo, phi);
+      term_pieces_e(t[j], e[j], h, plo, phi);
       atomicAdd((unsigned long long *)&mine[h], (unsigned long long)plo);
       atomicAdd((unsigned long long *)&mine[h + 1], (unsigned long long)phi);
     }
@@ -1197,22 +1201,47 @@ __device__ __forceinline__ void small_batch_add(long long *mine, unsigned long l
 // part, terms 2v and 2v + 1), so a batch still holds kSmallU terms per lane.
 constexpr int kPairV = kSmallU / 2;
 template <class Src>
-__device__ __forceinline__ void pair_batch_load(ulonglong2 (&v)[kPairV], const Src &src, long long a, long long vb,
-                                                long long nv, int lane) {
+__device__ __forceinline__ void pair_batch_load_whole(ulonglong2 (&v)[kPairV], const Src &src, long long a,
+                                                      long long vb, int lane) {
   const ulonglong2 *p = reinterpret_cast<const ulonglong2 *>(src.x + a);
-  if (vb + 64 * kPairV <= nv) {
 #pragma unroll
-    for (int j = 0; j < kPairV; j++) v[j] = stream_load(p + vb + lane + (long long)j * 64);
-  } else {
-    const long long last = nv - 1;
+  for (int j = 0; j < kPairV; j++) v[j] = stream_load(p + vb + lane + (long long)j * 64);
+  __builtin_amdgcn_sched_barrier(0);
+}
+// Any batch, whole or not: indices clamped to the last vector, so the loads
+// are issued unconditionally and there is no branch (whose join would make
+// the compiler's wait counts cover these loads before the batch in hand).
+template <class Src>
+__device__ __forceinline__ void pair_batch_load_clamped(ulonglong2 (&v)[kPairV], const Src &src, long long a,
+                                                        long long vb, long long nv, int lane) {
+  const ulonglong2 *p = reinterpret_cast<const ulonglong2 *>(src.x + a);
+  const long long last = nv - 1;
 #pragma unroll
-    for (int j = 0; j < kPairV; j++) {
-      long long i = vb + (long long)j * 64 + lane;
-      i = i < last ? i : last;
-      v[j] = stream_load(p + i);
-    }
+  for (int j = 0; j < kPairV; j++) {
+    long long i = vb + (long long)j * 64 + lane;
+    i = i < last ? i : last;
+    v[j] = stream_load(p + i);
   }
   __builtin_amdgcn_sched_barrier(0);
+}
+template <class Src>
+__device__ __forceinline__ void pair_batch_load(ulonglong2 (&v)[kPairV], const Src &src, long long a, long long vb,
+                                                long long nv, int lane) {
+  if (vb + 64 * kPairV <= nv)
+    pair_batch_load_whole(v, src, a, vb, lane);
+  else
+    pair_batch_load_clamped(v, src, a, vb, nv, lane);
+}
+template <class Src>
+__device__ __forceinline__ void pair_batch_add_whole(long long *mine, unsigned long long *spec, const Src &src,
+                                                     const ulonglong2 (&v)[kPairV]) {
+  unsigned long long t[kSmallU];
+#pragma unroll
+  for (int j = 0; j < kPairV; j++) {
+    t[2 * j] = src.sterm(v[j].x);
+    t[2 * j + 1] = src.sterm(v[j].y);
+  }
+  small_terms_add(mine, spec, t);
 }
 template <class Src>
 __device__ __forceinline__ void pair_batch_add(long long *mine, unsigned long long *spec, const Src &src,
@@ -1257,34 +1286,52 @@ __device__ __forceinline__ void pair_range_begin(PairRange<Src> &r, const Src &s
   r.fix = (lane == 0 && head) || (lane == 1 && tail);
   // the edge loads are clamped into the range, so issued unconditionally
   r.fr = src.sload_nt(lane == 1 ? hi - 1 : lo);
-  if (r.nv > 0) pair_batch_load(r.A, src, r.a, 0, r.nv, lane);
+  if (r.nv > 0) pair_batch_load_clamped(r.A, src, r.a, 0, r.nv, lane);
 }
 template <int COPIES, class Src>
 __device__ __forceinline__ void pair_range_add(long long *acc, unsigned long long *spec, const Src &src,
                                                PairRange<Src> &r, int lane) {
   constexpr int kEvery = 3 * COPIES;             // as in small_wave_accumulate
+  constexpr long long kVB = 64 * kPairV;
   long long *mine = acc + 68 * (lane % COPIES);
+  int batches = 0;
+  const auto tick = [&]() {
+    if (++batches == kEvery) {
+      batches = 0;
+      small_carry_all<COPIES>(acc, lane);
+    }
+  };
   if (r.nv > 0) {
-    constexpr long long kVB = 64 * kPairV;
     ulonglong2 B[kPairV];
-    int batches = 0;
-    for (long long vb = 0;;) {
-      pair_batch_load(B, src, r.a, vb + kVB, r.nv, lane);
+    long long vb = 0;
+    // Steady state: each pass loads and adds two whole batches, the next
+    // batch's loads in flight during each add, with no clamps or masks.
+    // It always leaves the batch in hand in r.A.
+    while (vb + 3 * kVB <= r.nv) {
+      pair_batch_load_whole(B, src, r.a, vb + kVB, lane);
+      pair_batch_add_whole(mine, spec, src, r.A);
+      tick();
+      pair_batch_load_whole(r.A, src, r.a, vb + 2 * kVB, lane);
+      pair_batch_add_whole(mine, spec, src, B);
+      tick();
+      vb += 2 * kVB;
+    }
+    // r.A holds the batch at vb; at most two follow, the last maybe ragged.
+    if (vb + kVB < r.nv) {
+      pair_batch_load_clamped(B, src, r.a, vb + kVB, r.nv, lane);
+      pair_batch_add_whole(mine, spec, src, r.A);
+      tick();
+      vb += kVB;
+      if (vb + kVB < r.nv) {
+        pair_batch_load_clamped(r.A, src, r.a, vb + kVB, r.nv, lane);
+        pair_batch_add_whole(mine, spec, src, B);
+        tick();
+        pair_batch_add(mine, spec, src, r.A, vb + kVB, r.nv, lane);
+      } else {
+        pair_batch_add(mine, spec, src, B, vb, r.nv, lane);
+      }
+    } else {
       pair_batch_add(mine, spec, src, r.A, vb, r.nv, lane);
-      vb += kVB;
-      if (++batches == kEvery) {
-        batches = 0;
-        small_carry_all<COPIES>(acc, lane);
-      }
-      if (vb >= r.nv) break;
-      pair_batch_load(r.A, src, r.a, vb + kVB, r.nv, lane);
-      pair_batch_add(mine, spec, src, B, vb, r.nv, lane);
-      vb += kVB;
-      if (++batches == kEvery) {
-        batches = 0;
-        small_carry_all<COPIES>(acc, lane);
-      }
-      if (vb >= r.nv) break;
     }
   }
   const unsigned long long ft[1] = {r.fix ? src.sterm(r.fr) : 0ull};

@@ -142,17 +142,27 @@ __device__ __forceinline__ void mantissa_sum_pieces(unsigned int ix, unsigned lo
 // (-1)^s M is shifted left by e_eff & 31, plo is the low 32 bits of that
 // (0 <= plo < 2^32, for chunk h) and phi the rest, an arithmetic shift
 // (|phi| < 2^52, for chunk h+1).  The sign is applied once, without a branch
-// (Discussion), before the split.
-__device__ __forceinline__ void term_pieces(unsigned long long b, int &h, long long &plo, long long &phi) {
-  const unsigned int e = (unsigned int)(b >> 52) & 2047u;
-  const unsigned long long M = (b & ((1ull << 52) - 1)) | ((unsigned long long)(e != 0) << 52);
-  const unsigned int e_eff = e ? e : 1u;
+// (Discussion), before the split.  The exponent field e is taken apart from
+// the rest so that a caller can test it for the special value 2047 first
+// and reuse it here.
+__device__ __forceinline__ unsigned int term_exp(unsigned long long b) {
+  return __builtin_amdgcn_ubfe((unsigned int)(b >> 32), 20u, 11u);
+}
+__device__ __forceinline__ void term_pieces_e(unsigned long long b, unsigned int e, int &h, long long &plo,
+                                              long long &phi) {
+  const unsigned int e_eff = e > 1u ? e : 1u;
+  const unsigned int hidden = e < 1u ? e : 1u;                       // 0 for a denormal
+  const unsigned int mhi = (hidden << 20) | ((unsigned int)(b >> 32) & 0xFFFFFu);
+  const unsigned long long M = ((unsigned long long)mhi << 32) | (unsigned int)b;
   const unsigned int lo = e_eff & 31u;
-  h = (int)(e_eff >> 5);
+  h = (int)__builtin_amdgcn_ubfe(e_eff, 5u, 6u);
   const long long neg = (long long)b >> 63;          // 0 or -1
   const long long Ms = (long long)((M ^ (unsigned long long)neg) - (unsigned long long)neg);
   plo = (long long)(unsigned int)((unsigned int)(unsigned long long)Ms << lo);
   phi = Ms >> (32 - lo);
+}
+__device__ __forceinline__ void term_pieces(unsigned long long b, int &h, long long &plo, long long &phi) {
+  term_pieces_e(b, term_exp(b), h, plo, phi);
 }
 
 __device__ __forceinline__ bool is_special(unsigned long long b) {

@@ -341,17 +341,40 @@ __global__ __launch_bounds__(BLOCK) void seg_short_kernel(const double *__restri
     }
     total = __builtin_amdgcn_readfirstlane(total);
     __syncthreads();
-    for (;;) {
-      // every lane adds 1, so one claim advances the counter by 64 and the
-      // first lane's old value (wave-uniform) names the claimed entry; no
-      // value of one lane is broadcast, and the loop stays scalar
+    // Every lane adds 1, so one claim advances the counter by 64 and the
+    // first lane's old value (wave-uniform) names the claimed entry; no
+    // value of one lane is broadcast, and every loop and branch stays scalar.
+    const auto claim = [&](int &j, long long &a, long long &b) -> bool {
       const int k = __builtin_amdgcn_readfirstlane(atomicAdd(&S.cnt, 1)) >> 6;
-      if (k >= total) break;
-      const int j = __builtin_amdgcn_readfirstlane(S.ord[k]);
-      const long long a = uniform_i64(S.lo[j]), b = uniform_i64(S.hi[j]);
-      // the accumulator is cleared under the segment's first loads
-      small_wave_accumulate<kShortCopies, SrcF64, true>(acc, spec, SrcF64{x}, a, b, lane, true);
+      if (k >= total) return false;
+      j = __builtin_amdgcn_readfirstlane(S.ord[k]);
+      a = uniform_i64(S.lo[j]);
+      b = uniform_i64(S.hi[j]);
+      return true;
+    };
+    // A segment's first loads are issued as soon as the previous segment's
+    // last batch has been added, so they are in flight while that segment
+    // is finished and rounded; the accumulator is cleared under them.
+    const SrcF64 src{x};
+    int j = 0;
+    long long a = 0, b = 0;
+    PairRange<SrcF64> R;
+    bool have = claim(j, a, b);
+    if (have && b > a) pair_range_begin(R, src, a, b, lane);
+    small_wave_zero<kShortCopies>(acc, spec, lane);
+    while (have) {
+      if (b > a) pair_range_add<kShortCopies>(acc, spec, src, R, lane);
+      int j1 = 0;
+      long long a1 = 0, b1 = 0;
+      const bool next = claim(j1, a1, b1);
+      if (next && b1 > a1) pair_range_begin(R, src, a1, b1, lane);
+      small_wave_finish<kShortCopies>(acc, lane, b - a < 1024);
       wave_merge_and_round(acc, spec, nullptr, 1u, &out[r0 + j], lane);
+      if (!next) break;
+      small_wave_zero<kShortCopies>(acc, spec, lane);
+      j = j1;
+      a = a1;
+      b = b1;
     }
     __syncthreads();
   }
