@@ -1099,11 +1099,19 @@ __device__ __forceinline__ void carry_step(long long *c, int lane) {
 // COPIES copies of 68 chunks (small_acc_words<COPIES>() words in LDS); lane l
 // adds into copy l % COPIES, so the 64 lanes' adds to one chunk land on
 // several addresses instead of one (same-address LDS atomics serialise).
-// The copies sit 544 bytes apart (copy-major: they measured fewer LDS bank
-// conflicts than copies interleaved per chunk).  After small_wave_accumulate
-// the first 68 words hold the plain 68 chunks.
+// The copies are copy-major (they measured fewer LDS bank conflicts than
+// copies interleaved per chunk), copy_words<COPIES>() 64-bit words apart.
+// A 64-bit word w sits on the bank pair w mod 32 of the 64 banks, so copy c
+// puts chunk h on pair (stride c + h) mod 32.  With 8 copies the stride is
+// 68 (4c: distinct for c < 8); with 16 it is 70 (6c: 16 distinct even
+// pairs, where 68 would give copies c and c + 8 the same pairs), so for
+// terms on two neighbouring chunks (h of either parity) no two copies
+// share a bank pair and only lanes of one copy on one chunk meet.  After
+// small_wave_accumulate the first 68 words hold the plain 68 chunks.
 template <int COPIES>
-constexpr int small_acc_words() { return 68 * COPIES; }
+constexpr int copy_words() { return COPIES > 8 ? 70 : 68; }
+template <int COPIES>
+constexpr int small_acc_words() { return copy_words<COPIES>() * COPIES; }
 
 // Zero a wave's accumulator copies and side words.
 template <int COPIES>
@@ -1259,7 +1267,7 @@ __device__ __forceinline__ void pair_batch_add(long long *mine, unsigned long lo
 template <int COPIES>
 __device__ __forceinline__ void small_carry_all(long long *acc, int lane) {
 #pragma unroll
-  for (int c = 0; c < COPIES; c++) carry_step(acc + 68 * c, lane);
+  for (int c = 0; c < COPIES; c++) carry_step(acc + copy_words<COPIES>() * c, lane);
 }
 
 // One wave's pass over a range [lo, hi) (hi > lo) of a kPairs source, split
@@ -1293,7 +1301,7 @@ __device__ __forceinline__ void pair_range_add(long long *acc, unsigned long lon
                                                PairRange<Src> &r, int lane) {
   constexpr int kEvery = 3 * COPIES;             // as in small_wave_accumulate
   constexpr long long kVB = 64 * kPairV;
-  long long *mine = acc + 68 * (lane % COPIES);
+  long long *mine = acc + copy_words<COPIES>() * (lane % COPIES);
   int batches = 0;
   const auto tick = [&]() {
     if (++batches == kEvery) {
@@ -1350,8 +1358,8 @@ __device__ __forceinline__ void small_wave_finish(long long *acc, int lane, bool
     long long t0 = 0, t1 = 0;
 #pragma unroll
     for (int c = 0; c < COPIES; c++) {
-      t0 += acc[68 * c + lane];
-      if (lane < 4) t1 += acc[68 * c + 64 + lane];
+      t0 += acc[copy_words<COPIES>() * c + lane];
+      if (lane < 4) t1 += acc[copy_words<COPIES>() * c + 64 + lane];
     }
     __builtin_amdgcn_wave_barrier();
     acc[lane] = t0;
@@ -1378,7 +1386,7 @@ __device__ __forceinline__ void small_wave_accumulate(long long *acc, unsigned l
   // 1536 * 2^52 < 2^63
   constexpr int kEvery = 3 * COPIES;
   static_assert(64 % COPIES == 0 && kEvery * kSmallU * (64 / COPIES) <= 1536, "carry interval");
-  long long *mine = acc + 68 * (lane % COPIES);
+  long long *mine = acc + copy_words<COPIES>() * (lane % COPIES);
   if (ZERO && !(hi > lo)) small_wave_zero<COPIES>(acc, spec, lane);
   if constexpr (Src::kPairs) {
     if (hi > lo) {

@@ -168,7 +168,7 @@ __global__ __launch_bounds__(BLOCK) void seg_long_kernel(const double *__restric
   long_phase<BLOCK, VEC, DEPTH>(S, x, offsets, nseg, out, accs, small_max, precombine);
 }
 
-constexpr int kShortCopies = 8;
+constexpr int kShortCopies = 16;
 constexpr int kShortBlock = 1024;      // one workgroup per compute unit
 // Long segments: workgroups of 256 threads, two per compute unit, so that
 // one streams while the other flushes and rounds a segment (measured on the
@@ -207,8 +207,7 @@ template <int BLOCK>
 struct ShortShared {
   long long acc[BLOCK / 64][small_acc_words<kShortCopies>()];
   unsigned long long spec[BLOCK / 64][4];
-  long long lo[BLOCK];                 // a round's segment bounds (also scan scratch)
-  long long hi[BLOCK];
+  long long lo[BLOCK + 1];             // a round's segment starts and its end (also scan scratch)
   int ord[BLOCK];                      // the round's short segments, longest class first
   int ccount[3][BLOCK / 64];
   int cnt;                             // 64 x the next entry of ord to hand out
@@ -313,9 +312,12 @@ __global__ __launch_bounds__(BLOCK) void seg_short_kernel(const double *__restri
       s1 = offsets[i + 1];
       const long long len = s1 - s0;
       if (len <= small_max) cls = len >= kClassA ? 0 : (len >= kClassB ? 1 : 2);
+    } else if (i == g1) {
+      s0 = offsets[i];
     }
+    // segment r0 + j of the round is [lo[j], lo[j + 1])
     S.lo[tid] = s0;
-    S.hi[tid] = s1;
+    if (tid == BLOCK - 1) S.lo[BLOCK] = s1;
     const unsigned long long m0 = __ballot(cls == 0), m1 = __ballot(cls == 1), m2 = __ballot(cls == 2);
     if (lane == 0) {
       S.ccount[0][wave] = __popcll(m0);
@@ -349,7 +351,7 @@ __global__ __launch_bounds__(BLOCK) void seg_short_kernel(const double *__restri
       if (k >= total) return false;
       j = __builtin_amdgcn_readfirstlane(S.ord[k]);
       a = uniform_i64(S.lo[j]);
-      b = uniform_i64(S.hi[j]);
+      b = uniform_i64(S.lo[j + 1]);
       return true;
     };
     // A segment's first loads are issued as soon as the previous segment's
