@@ -287,7 +287,10 @@ int exsum_segmented_f64(const double *x, const int64_t *offsets, int64_t nseg, d
                                                  c.seg_small_max, c.precombine, c.seg_group));
   }
   int grid = c.seg_grid;
-  if (grid == 0) grid = 2 * cu_count(dev);           // two long-segment workgroups per compute unit
+  // long segments: twelve workgroups per compute unit (three fit at once),
+  // so that the dispatcher hands more of the evenly split term ranges to
+  // compute units whose ranges hold fewer long segments
+  if (grid == 0) grid = std::min(12 * cu_count(dev), kMaxGrid);
   // short segments: one workgroup per compute unit
   const int short_grid = std::min(cu_count(dev), seg_short_block());
   return status_of(launch_segmented(x, offsets, nseg, out, accs, chunks, s, grid, short_grid, c.seg_small_max,

@@ -473,50 +473,96 @@ struct SrcDotF32 {
 // loads in flight in a ring of register buffers.  Every wave runs the same
 // number of full tiles (count mode puts a workgroup barrier after each); the
 // leftover positions of each stream form one last, partial tile.
+// One tile's loads for a wave's stream (an index past the last full tile
+// reads the pad tile, so loads are unconditional: the compiler's wait
+// counts stay exact and a prefetch is never waited for early).
+template <int VEC, class Src>
+__device__ __forceinline__ void large_tile_load(typename Src::Vec (&bf)[VEC], const Src &src, long long a,
+                                                long long ws, long long ntiles, long long t, int lane) {
+  constexpr int TILE_W = 64 * VEC;
+  const typename Src::Ptr tp = (t < ntiles) ? src.at(a, ws + t * TILE_W) : Src::pad();
+#pragma unroll
+  for (int j = 0; j < VEC; j++) bf[j] = Src::load(tp, lane + j * 64);
+  // keep the scheduler from hoisting work on other buffers above these
+  // loads (which would force an early wait on them)
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// A range split into begin and add, so that a caller can issue a range's
+// first loads (its scalar edge terms and first DEPTH tiles) while it still
+// finishes another range, and add the range later.
+template <int VEC, int DEPTH, class Src>
+struct LargeRange {
+  long long a;                  // first vector position's term
+  long long nv;                 // vector positions
+  long long ws, we;             // this wave's stream of positions
+  long long ntiles;             // full tiles per stream
+  long long head, tail;         // scalar edge terms
+  typename Src::Raw hr;         // this lane's edge term, as loaded
+  bool hvalid;
+  typename Src::Vec buf[DEPTH][VEC];
+};
+
+template <int BLOCK, int VEC, int DEPTH, class Src>
+__device__ __forceinline__ void large_range_begin(LargeRange<VEC, DEPTH, Src> &R, const Src &src, long long r0,
+                                                  long long r1) {
+  constexpr int T = Src::kTPV;
+  constexpr int NW = BLOCK / 64;
+  constexpr int TILE_W = 64 * VEC;            // positions per wave per tile
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (r1 <= r0) {
+    R.a = r0;
+    R.nv = R.ws = R.we = R.ntiles = R.head = R.tail = 0;
+    R.hvalid = false;
+    return;
+  }
+  long long head = src.head_terms(r0);
+  if (head > r1 - r0) head = r1 - r0;
+  R.head = head;
+  R.a = r0 + head;
+  R.nv = (r1 - R.a) / T;
+  R.tail = (r1 - R.a) - R.nv * T;
+  // scalar terms (at most 2(T-1), on the first lanes of wave 0): loaded now,
+  // added last
+  R.hr = typename Src::Raw{};
+  R.hvalid = false;
+  if (tid < head) {
+    R.hr = src.sload(r0 + tid);
+    R.hvalid = true;
+  } else if (tid < head + R.tail) {
+    R.hr = src.sload(r1 - R.tail + (tid - head));
+    R.hvalid = true;
+  }
+  const long long q = R.nv / NW;                     // positions per stream (the last takes the rest)
+  R.ws = (long long)wave * q;
+  R.we = (wave == NW - 1) ? R.nv : R.ws + q;
+  R.ntiles = q / TILE_W;                             // full tiles, the same for every wave
+  static_assert(VEC <= kMaxVec && VEC + 1 <= kMaxSlots, "pad tile or slow tile too small");
+  if (R.ntiles > 0) {
+#pragma unroll
+    for (int d = 0; d < DEPTH; d++) large_tile_load<VEC>(R.buf[d], src, R.a, R.ws, R.ntiles, d, lane);
+  }
+}
+
+// Add the source's terms r0 .. r1 into the workgroup's large accumulator.
+// Terms before the first 16-byte-aligned position and after the last whole
+// one are added as scalars.  The vector positions are split into one
+// contiguous stream per wavefront; a wave's tile is 64*VEC positions (each
+// load instruction covers 1 KiB per input), with the next DEPTH tiles'
+// loads in flight in a ring of register buffers.  Every wave runs the same
+// number of full tiles (count mode puts a workgroup barrier after each); the
+// leftover positions of each stream form one last, partial tile.
 template <int BLOCK, int VEC, int DEPTH, int MODE, class Src>
-__device__ __forceinline__ void accumulate_range(LargeShared &S, const Src &src, long long r0, long long r1,
-                                                 int precombine, unsigned int &tile) {
+__device__ __forceinline__ void large_range_add(LargeShared &S, LargeRange<VEC, DEPTH, Src> &R, const Src &src,
+                                                int precombine, unsigned int &tile) {
   constexpr int T = Src::kTPV;
   constexpr int NW = BLOCK / 64;
   constexpr int TILE_W = 64 * VEC;            // positions per wave per tile
   constexpr int TILE_V = BLOCK * VEC;         // positions per workgroup per tile
   static_assert(MODE != kCountMode || T * TILE_V < kCap, "tile too large for the count bound");
   constexpr unsigned int THR = (MODE == kCountMode) ? (unsigned int)(kCap - T * TILE_V) : 0u;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (r1 <= r0) return;
-  long long head = src.head_terms(r0);
-  if (head > r1 - r0) head = r1 - r0;
-  const long long a = r0 + head;
-  const long long nv = (r1 - a) / T;
-  const long long tail = (r1 - a) - nv * T;
-  // scalar terms (at most 2(T-1), on the first lanes of wave 0): loaded now,
-  // added last
-  typename Src::Raw hr{};
-  bool hvalid = false;
-  if (tid < head) {
-    hr = src.sload(r0 + tid);
-    hvalid = true;
-  } else if (tid < head + tail) {
-    hr = src.sload(r1 - tail + (tid - head));
-    hvalid = true;
-  }
-  const long long q = nv / NW;                       // positions per stream (the last takes the rest)
-  const long long ws = (long long)wave * q;
-  const long long we = (wave == NW - 1) ? nv : ws + q;
-  const long long ntiles = q / TILE_W;               // full tiles, the same for every wave
-  // Loads are unconditional (an index past the last tile reads the pad tile)
-  // so the compiler's wait counts stay exact and a prefetch is never waited
-  // for early.
-  static_assert(VEC <= kMaxVec && VEC + 1 <= kMaxSlots, "pad tile or slow tile too small");
-  typename Src::Vec buf[DEPTH][VEC];
-  auto load = [&](typename Src::Vec(&bf)[VEC], long long t) {
-    const typename Src::Ptr tp = (t < ntiles) ? src.at(a, ws + t * TILE_W) : Src::pad();
-#pragma unroll
-    for (int j = 0; j < VEC; j++) bf[j] = Src::load(tp, lane + j * 64);
-    // keep the scheduler from hoisting work on other buffers above these
-    // loads (which would force an early wait on them)
-    __builtin_amdgcn_sched_barrier(0);
-  };
+  const int tid = threadIdx.x, lane = tid & 63;
+  const long long a = R.a, ws = R.ws, we = R.we, ntiles = R.ntiles;
   auto process = [&](const typename Src::Vec(&bf)[VEC], long long t) {
     unsigned long long b[T * VEC];
 #pragma unroll
@@ -531,26 +577,33 @@ __device__ __forceinline__ void accumulate_range(LargeShared &S, const Src &src,
     tile_end<MODE>(S, tile++, tid);
   };
   if (ntiles > 0) {
-#pragma unroll
-    for (int d = 0; d < DEPTH; d++) load(buf[d], d);
     for (long long t = 0; t < ntiles; t += DEPTH) {
 #pragma unroll
       for (int d = 0; d < DEPTH; d++) {
-        if (d == 0 || t + d < ntiles) process(buf[d], t + d);
-        load(buf[d], t + d + DEPTH);
+        if (d == 0 || t + d < ntiles) process(R.buf[d], t + d);
+        large_tile_load<VEC>(R.buf[d], src, a, ws, ntiles, t + d + DEPTH, lane);
       }
     }
   }
   // leftover: fewer than TILE_W positions per stream (plus up to NW-1 more
   // in the last), so at most VEC+1 slots and fewer terms than one full tile
-  if (nv > (long long)NW * ntiles * TILE_W) {
+  if (R.nv > (long long)NW * ntiles * TILE_W) {
     slow_tile<MODE, Src>(&S, src, a, ws + ntiles * TILE_W + lane, we, 64, VEC + 1, precombine, tile, THR);
     tile_end<MODE>(S, tile++, tid);
   }
-  if (head || tail) {
-    add_slot<MODE>(S, hvalid ? src.sterm(hr) : 0ull, hvalid, precombine, tile, lane, THR);
+  if (R.head || R.tail) {
+    add_slot<MODE>(S, R.hvalid ? src.sterm(R.hr) : 0ull, R.hvalid, precombine, tile, lane, THR);
     tile_end<MODE>(S, tile++, tid);
   }
+}
+
+template <int BLOCK, int VEC, int DEPTH, int MODE, class Src>
+__device__ __forceinline__ void accumulate_range(LargeShared &S, const Src &src, long long r0, long long r1,
+                                                 int precombine, unsigned int &tile) {
+  if (r1 <= r0) return;
+  LargeRange<VEC, DEPTH, Src> R;
+  large_range_begin<BLOCK>(R, src, r0, r1);
+  large_range_add<BLOCK, VEC, DEPTH, MODE>(S, R, src, precombine, tile);
 }
 
 // Transfer every used chunk into S.small.  Group gi holds the 64 chunks whose

@@ -99,6 +99,8 @@ __device__ __forceinline__ void long_phase(SegShared &S, const double *__restric
   __syncthreads();
   long long i = S.first;
   unsigned int tile = 0;
+  const SrcF64 src{x};
+  LargeRange<VEC, DEPTH, SrcF64> R;
 
   while (i < nseg) {
     const int cnt = (int)((nseg - i < kSegBatch) ? (nseg - i) : kSegBatch);
@@ -109,13 +111,28 @@ __device__ __forceinline__ void long_phase(SegShared &S, const double *__restric
     for (int k = tid; k < cnt; k += BLOCK)
       if (S.off[k] >= hi_w) atomicMin(&S.nb, (unsigned int)k);
     __syncthreads();
-    const int nb = (int)S.nb;
-    for (int k = 0; k < nb; k++) {
-      const long long s0 = S.off[k], s1 = S.off[k + 1];
-      if (s1 - s0 <= small_max) continue;              // short: summed elsewhere
-      const long long a = s0 > lo_w ? s0 : lo_w;
-      const long long b = s1 < hi_w ? s1 : hi_w;
-      accumulate_range<BLOCK, VEC, DEPTH, kCarryMode>(S.L, SrcF64{x}, a, b, precombine, tile);
+    // every value that steers the loop below is read from LDS through
+    // readfirstlane, so the compiler sees it wave-uniform (the loop holds
+    // workgroup barriers)
+    const int nb = __builtin_amdgcn_readfirstlane((int)S.nb);
+    // the next long segment of the batch from k on (short ones are summed
+    // elsewhere), and its piece in this range
+    const auto next_long = [&](int k) {
+      while (k < nb && uniform_i64(S.off[k + 1]) - uniform_i64(S.off[k]) <= small_max) k++;
+      return k;
+    };
+    const auto piece_begin = [&](int k) {
+      const long long s0 = uniform_i64(S.off[k]), s1 = uniform_i64(S.off[k + 1]);
+      large_range_begin<BLOCK>(R, src, s0 > lo_w ? s0 : lo_w, s1 < hi_w ? s1 : hi_w);
+    };
+    int k = next_long(0);
+    if (k < nb) piece_begin(k);
+    while (k < nb) {
+      const long long s0 = uniform_i64(S.off[k]), s1 = uniform_i64(S.off[k + 1]);
+      large_range_add<BLOCK, VEC, DEPTH, kCarryMode>(S.L, R, src, precombine, tile);
+      // the next piece's first loads fly while this one is flushed and rounded
+      const int kn = next_long(k + 1);
+      if (kn < nb) piece_begin(kn);
       final_flush<BLOCK, true, kCarryMode>(S.L);
       const bool split = (s0 < lo_w) || (s1 > hi_w);
       unsigned int expected = 1;
@@ -129,6 +146,7 @@ __device__ __forceinline__ void long_phase(SegShared &S, const double *__restric
       if (tid < 68) S.L.small[tid] = 0;
       if (tid < 3) S.L.spec[tid] = 0ull;
       __syncthreads();
+      k = kn;
     }
     if (nb < cnt) break;                               // the range ended inside this batch
     i += cnt;
@@ -170,10 +188,10 @@ __global__ __launch_bounds__(BLOCK) void seg_long_kernel(const double *__restric
 
 constexpr int kShortCopies = 16;
 constexpr int kShortBlock = 1024;      // one workgroup per compute unit
-// Long segments: workgroups of 256 threads, two per compute unit, so that
-// one streams while the other flushes and rounds a segment (measured on the
-// 65,536-segment batch: 436 us against 480-530 us for one 512-thread
-// workgroup per compute unit).
+// Long segments: workgroups of 256 threads, several per compute unit, so
+// that one streams while another flushes and rounds a segment (measured on
+// the 65,536-segment batch: 436 us with two against 480-530 us for one
+// 512-thread workgroup per compute unit).
 constexpr int kLongBlock = 256;
 // Length classes: a round's segments are handed out longest class first.
 constexpr long long kClassA = 4096, kClassB = 512;
