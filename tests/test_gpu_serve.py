@@ -157,3 +157,25 @@ def test_replay_2000_requests_every_result_against_the_oracle(ex):
     out2 = torch.full((nreq,), np.nan, dtype=torch.float64, device="cuda:0")
     ex.exsum_serial_replay(pt, starts, lens, arrival, out2)
     assert np.array_equal(bits(out2), want)
+
+
+def test_inputs_written_on_the_stream_are_seen(ex):
+    """The server's steps run in order on its stream: inputs filled with NaN
+    and then overwritten by a copy on that stream, submitted without any
+    synchronisation, are summed from the copy."""
+    pool, starts, lens = pool_and_requests(4)
+    want = oracle.sum_ranges_f64(pool, starts, lens)
+    src = torch.from_numpy(pool).to("cuda:0")
+    out = torch.full((lens.size,), np.nan, dtype=torch.float64, device="cuda:0")
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        buf = torch.full_like(src, np.nan)
+        with ex.Server(tiny_cfg(ex), stream=side) as srv:
+            for rep in range(3):
+                buf.fill_(np.nan)
+                buf.copy_(src)
+                for i, (s0, L) in enumerate(zip(starts, lens)):
+                    srv.submit(buf[s0:s0 + L], out, i)
+                srv.drain()
+                assert np.array_equal(bits(out), want), rep
