@@ -1395,8 +1395,11 @@ __device__ __forceinline__ void pair_range_add(long long *acc, unsigned long lon
       pair_batch_add(mine, spec, src, r.A, vb, r.nv, lane);
     }
   }
-  const unsigned long long ft[1] = {r.fix ? src.sterm(r.fr) : 0ull};
-  small_terms_add(mine, spec, ft);
+  // the edge terms: lanes 0 and 1 only (the others would add zeros)
+  if (r.fix) {
+    const unsigned long long ft[1] = {src.sterm(r.fr)};
+    small_terms_add(mine, spec, ft);
+  }
 }
 
 // The end of a wave's sum: carry steps of the copies (skipped when the range
@@ -1404,21 +1407,55 @@ __device__ __forceinline__ void pair_range_add(long long *acc, unsigned long lon
 // the copies added into the first 68 words.
 template <int COPIES>
 __device__ __forceinline__ void small_wave_finish(long long *acc, int lane, bool skip_carry) {
-  if (!skip_carry) small_carry_all<COPIES>(acc, lane);
-  if (COPIES > 1) {
-    // every copy is below 2^33 after its carry (below 1023 * 2^52 without)
-    __builtin_amdgcn_wave_barrier();
+  if (COPIES == 1) {
+    if (!skip_carry) carry_step(acc, lane);
+    return;
+  }
+  __builtin_amdgcn_wave_barrier();
+  long long A, B = 0;
+  if (skip_carry) {
+    // the copies' total stays below 1023 * 2^52 (see small_wave_accumulate)
     long long t0 = 0, t1 = 0;
 #pragma unroll
     for (int c = 0; c < COPIES; c++) {
       t0 += acc[copy_words<COPIES>() * c + lane];
       if (lane < 4) t1 += acc[copy_words<COPIES>() * c + 64 + lane];
     }
-    __builtin_amdgcn_wave_barrier();
-    acc[lane] = t0;
-    if (lane < 4) acc[64 + lane] = t1;
-    __builtin_amdgcn_wave_barrier();
+    A = t0;
+    B = t1;
+  } else {
+    // The copies are added with one parallel carry step folded in, in one
+    // pass: every word (below 2^63) splits into its low 32 bits, which stay
+    // in its chunk, and its high part, which moves one chunk up (chunk 66
+    // keeps its high part).  Over the copies the low sums stay below
+    // COPIES * 2^32 and the high sums below COPIES * 2^31 in magnitude, so
+    // nothing wraps; the value is the copies' total, with every chunk below
+    // 2^38.
+    long long lo0 = 0, hi0 = 0, lo1 = 0, hi1 = 0;
+#pragma unroll
+    for (int c = 0; c < COPIES; c++) {
+      const long long v0 = acc[copy_words<COPIES>() * c + lane];
+      lo0 += v0 & 0xFFFFFFFFll;
+      hi0 += v0 >> 32;
+      if (lane < 4) {
+        const long long v1 = acc[copy_words<COPIES>() * c + 64 + lane];
+        lo1 += v1 & 0xFFFFFFFFll;
+        hi1 += v1 >> 32;
+      }
+    }
+    // chunk i receives the high sum of chunk i - 1 (lane i - 1 of the
+    // 64-chunk row; chunk 64 from lane 63)
+    const long long cA = (long long)shr1_u64((unsigned long long)hi0, 0ull);
+    const long long hiA63 = (long long)readlane_u64((unsigned long long)hi0, 63);
+    const long long cB = (long long)shr1_u64((unsigned long long)hi1, (unsigned long long)hiA63);
+    A = lo0 + cA;
+    if (lane < 2) B = lo1 + cB;
+    else if (lane == 2) B = lo1 + hi1 * 4294967296ll + cB;
   }
+  __builtin_amdgcn_wave_barrier();
+  acc[lane] = A;
+  if (lane < 4) acc[64 + lane] = B;
+  __builtin_amdgcn_wave_barrier();
 }
 
 // Wave adds the source's terms lo .. hi into acc (small_acc_words<COPIES>()
