@@ -224,3 +224,50 @@ def test_wrapper_validates_offsets_and_empty_input(ex):
     ex.exsum_segmented_f64(empty, off, out=out)
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy().view(np.uint64), np.zeros(5, dtype=np.uint64))
+
+
+def test_small_body_top_chunks(ex):
+    """One-wave sums of 1023 to 30,000 terms whose pieces fall on the top
+    chunks (terms of magnitude 2^1000 to 2^1024): the copies' final carry,
+    folded into their sum, carries across the 64th chunk and into the top
+    one.  Random signs, all positive (an exact sum above DBL_MAX rounds to
+    +inf), and cancelling pairs with a small remainder, as short segments
+    (default threshold, and 65536 so that a 30,000-term segment also gets
+    the periodic carries) and as single sums; every result against the
+    oracle."""
+    rng = np.random.default_rng(11)
+
+    def huge(n, sign):
+        v = np.ldexp(rng.uniform(1, 2, n), rng.integers(1000, 1024, n))
+        return v * (rng.choice([-1.0, 1.0], n) if sign else 1.0)
+
+    parts = []
+    for n in (1023, 1024, 1025, 2047, 4096, 8191, 12288):
+        parts.append(huge(n, True))
+        parts.append(huge(n, False))
+        h = huge(n // 2, False)
+        pair = np.empty(2 * h.size)
+        pair[0::2], pair[1::2] = h, -h
+        pair[rng.integers(0, pair.size, 3)] = [3.0, -0.5, 2.0 ** -1074]
+        parts.append(rng.permutation(pair))
+        # top chunks only just below overflow, with borrows from below
+        m = np.full(n, np.finfo(np.float64).max) * rng.choice([-1.0, 1.0], n)
+        m[::7] = -np.ldexp(1.0, 1000)
+        parts.append(m)
+    parts.append(huge(30000, True))
+    parts.append(np.concatenate([huge(15000, False), -huge(15000, False), [1.0]]))
+    lens = [p.size for p in parts]
+    x = np.concatenate(parts)
+    off = np.zeros(len(lens) + 1, dtype=np.int64)
+    np.cumsum(lens, out=off[1:])
+    want = oracle.segmented_f64(x, off)
+    xt, offt = dev(x), dev(off)
+    for sm in (12288, 65536):
+        for mode in (0, 1):
+            assert np.array_equal(seg_bits(ex, xt, offt, seg_small_max=sm, seg_mode=mode), want), (sm, mode)
+    out = torch.empty(1, dtype=torch.float64, device="cuda:0")
+    for k, p in enumerate(parts):
+        if 1024 <= p.size <= 4096:
+            ex.exsum_f64(dev(p), out=out)
+            torch.cuda.synchronize()
+            assert int(out.cpu().numpy().view(np.uint64)[0]) == int(oracle.sum_f64(p)), (k, p.size)
