@@ -1286,14 +1286,6 @@ __device__ __forceinline__ void pair_batch_load_clamped(ulonglong2 (&v)[kPairV],
   __builtin_amdgcn_sched_barrier(0);
 }
 template <class Src>
-__device__ __forceinline__ void pair_batch_load(ulonglong2 (&v)[kPairV], const Src &src, long long a, long long vb,
-                                                long long nv, int lane) {
-  if (vb + 64 * kPairV <= nv)
-    pair_batch_load_whole(v, src, a, vb, lane);
-  else
-    pair_batch_load_clamped(v, src, a, vb, nv, lane);
-}
-template <class Src>
 __device__ __forceinline__ void pair_batch_add_whole(long long *mine, unsigned long long *spec, const Src &src,
                                                      const ulonglong2 (&v)[kPairV]) {
   unsigned long long t[kSmallU];

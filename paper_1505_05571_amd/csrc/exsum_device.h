@@ -161,9 +161,6 @@ __device__ __forceinline__ void term_pieces_e(unsigned long long b, unsigned int
   plo = (long long)(unsigned int)((unsigned int)(unsigned long long)Ms << lo);
   phi = Ms >> (32 - lo);
 }
-__device__ __forceinline__ void term_pieces(unsigned long long b, int &h, long long &plo, long long &phi) {
-  term_pieces_e(b, term_exp(b), h, plo, phi);
-}
 
 __device__ __forceinline__ bool is_special(unsigned long long b) {
   return ((unsigned int)(b >> 32) & 0x7FF00000u) == 0x7FF00000u;
