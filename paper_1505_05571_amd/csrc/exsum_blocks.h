@@ -986,20 +986,22 @@ __device__ __forceinline__ void wait_memory() {
   __builtin_amdgcn_s_waitcnt(0);
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
-__device__ __forceinline__ unsigned int ticket_add(unsigned int *p) {
-  return __hip_atomic_fetch_add(p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ unsigned int ticket_add(unsigned int *p, unsigned int k = 1u) {
+  return __hip_atomic_fetch_add(p, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Merge into one accumulator (Discussion: add the parts' small
 // superaccumulators, round once).  A workgroup adds its 67 chunks into `g`
-// with 64-bit integer atomics (exact and order independent), takes a ticket,
-// and the one that completes the expected count reads and clears `g`, rounds,
-// and writes *out.  Called by every thread; returns true in the workgroup
-// that wrote the result.  Used where few parts meet (a segment cut by
-// workgroup boundaries), so the atomics see little contention.
+// with 64-bit integer atomics (exact and order independent), advances the
+// ticket by the number of parts its accumulator holds (`parts`), and the one
+// that completes the expected count reads and clears `g`, rounds, and writes
+// *out.  Called by every thread; returns true in the workgroup that wrote the
+// result.  Used where few parts meet (a segment cut by workgroup boundaries,
+// a served request's runs of pieces), so the atomics see little contention.
 __device__ __forceinline__ bool merge_and_round(long long *s_small, unsigned long long *spec,
                                                 unsigned int *s_ticket, GlobalAcc *__restrict__ g,
-                                                unsigned int expected, double *__restrict__ out) {
+                                                unsigned int expected, double *__restrict__ out,
+                                                unsigned int parts = 1u) {
   const int tid = threadIdx.x;
   __syncthreads();
   if (expected <= 1) {
@@ -1021,9 +1023,9 @@ __device__ __forceinline__ bool merge_and_round(long long *s_small, unsigned lon
   }
   wait_memory();
   __syncthreads();
-  if (tid == 0) *s_ticket = ticket_add(&g->ticket);
+  if (tid == 0) *s_ticket = ticket_add(&g->ticket, parts);
   __syncthreads();
-  const bool last = (*s_ticket == expected - 1);
+  const bool last = (*s_ticket + parts == expected);
   __syncthreads();
   if (!last) return false;
   if (tid < kSChunks) s_small[tid] = (long long)atomicExch(&g->chunk[tid], 0ull);

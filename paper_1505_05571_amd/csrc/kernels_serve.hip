@@ -64,17 +64,45 @@ __global__ __launch_bounds__(BLOCK) void piece_kernel(const Table P, int nshort,
   }
   __syncthreads();
 
-  // long pieces: one per workgroup
+  // long pieces: each workgroup takes a contiguous run of the list.  Pieces
+  // of one request lie next to each other in it (the scheduler gives the
+  // oldest requests their pieces in a row) and share a slot and an expected
+  // count, so a workgroup adds consecutive pieces of one request into its
+  // large accumulator and flushes and merges once for all of them, the
+  // ticket advancing by their number.  Every value that steers the loops
+  // below is made wave-uniform (they hold workgroup barriers).
+  const int nl = np - nshort;
+  const int q0 = nshort + (int)((long long)nl * blockIdx.x / gridDim.x);
+  const int q1 = nshort + (int)((long long)nl * (blockIdx.x + 1) / gridDim.x);
+  const auto key_of = [&](int q, unsigned int &expected, int &slot) {
+    const Piece pc = P[q];
+    expected = (unsigned int)__builtin_amdgcn_readfirstlane((int)pc.expected);
+    slot = __builtin_amdgcn_readfirstlane(pc.slot);
+  };
   unsigned int tile = 0;
-  for (int p = nshort + (int)blockIdx.x; p < np; p += (int)gridDim.x) {
+  for (int p = q0; p < q1;) {
+    unsigned int expected;
+    int slot;
+    key_of(p, expected, slot);
     const Piece pc = P[p];
-    accumulate_range<BLOCK, VEC, DEPTH, kCarryMode>(S.L, SrcF64{pc.x}, 0, pc.n, precombine, tile);
+    int q = p;
+    do {
+      const Piece pq = P[q];
+      accumulate_range<BLOCK, VEC, DEPTH, kCarryMode>(S.L, SrcF64{pq.x}, 0, pq.n, precombine, tile);
+      q++;
+      if (expected == 1u || q >= q1) break;
+      unsigned int e2;
+      int s2;
+      key_of(q, e2, s2);
+      if (e2 != expected || s2 != slot) break;
+    } while (true);
     final_flush<BLOCK, true, kCarryMode>(S.L);
-    GlobalAcc *g = pc.expected == 1u ? nullptr : &slots[pc.slot];
-    merge_and_round(S.L.small, S.L.spec, &S.L.ticket, g, pc.expected, pc.out);
+    GlobalAcc *g = expected == 1u ? nullptr : &slots[slot];
+    merge_and_round(S.L.small, S.L.spec, &S.L.ticket, g, expected, pc.out, (unsigned int)(q - p));
     if (tid < 68) S.L.small[tid] = 0;
     if (tid < 3) S.L.spec[tid] = 0ull;
     __syncthreads();
+    p = q;
   }
 }
 
