@@ -179,6 +179,27 @@ def test_server_plan_invariants(lib):
             plan_invariants(lens, cfg, plan)
 
 
+def test_server_plan_lays_out_a_requests_pieces_in_a_row(lib):
+    """Within a step, the pieces of one request after its first come in one
+    contiguous block of the list, in the order of its terms, so that the
+    piece kernel's workgroups meet them as runs (summed in one accumulator
+    and merged once)."""
+    import numpy as np
+    rng = np.random.default_rng(9)
+    lens = list(np.rint(10.0 ** rng.uniform(2, 5.5, size=60)).astype(np.int64))
+    for cfg in (small_cfg(step_terms=1 << 14), small_cfg(step_terms=1 << 16, max_pieces=400),
+                ex.exsum_server_default_config()):
+        plan = ex.exsum_server_plan(lens, cfg)
+        for s in np.unique(plan["step"]):
+            idx = np.nonzero(plan["step"] == s)[0]
+            req, off = plan["req"][idx], plan["off"][idx]
+            for r in np.unique(req):
+                pos = np.nonzero(req == r)[0]
+                rest = pos[1:]
+                assert np.all(np.diff(rest) == 1), (s, r)
+                assert np.all(np.diff(off[pos]) > 0), (s, r)
+
+
 def test_server_plan_shares_steps_fairly(lib):
     import numpy as np
     # a short request behind a long one is served in the first step
