@@ -1209,16 +1209,26 @@ __device__ __forceinline__ void small_batch_load(typename Src::Raw (&b)[kSmallU]
 // finite terms takes one branch-free path; only a batch holding an infinity
 // or NaN (exponent field 2047) goes term by term.
 template <int K>
+__device__ __forceinline__ unsigned int umax_of(const unsigned int (&e)[K]) {
+  unsigned int m = e[0];
+#pragma unroll
+  for (int j = 1; j < K; j++) m = m > e[j] ? m : e[j];
+  return m;
+}
+template <int K>
+__device__ __forceinline__ unsigned int umin_of(const unsigned int (&e)[K]) {
+  unsigned int m = e[0];
+#pragma unroll
+  for (int j = 1; j < K; j++) m = m < e[j] ? m : e[j];
+  return m;
+}
+template <int K>
 __device__ __forceinline__ void small_terms_add(long long *mine, unsigned long long *spec,
                                                 const unsigned long long (&t)[K]) {
   unsigned int e[K];
-  bool special = false;
 #pragma unroll
-  for (int j = 0; j < K; j++) {
-    e[j] = term_exp(t[j]);
-    special |= e[j] == 2047u;
-  }
-  if (!__any(special)) {
+  for (int j = 0; j < K; j++) e[j] = term_exp(t[j]);
+  if (!__any(umax_of(e) == 2047u)) {
 #pragma unroll
     for (int j = 0; j < K; j++) {
       int h;
@@ -1243,18 +1253,41 @@ __device__ __forceinline__ void small_terms_add(long long *mine, unsigned long l
   }
 }
 
+// The range of exponent fields of the terms a lane has loaded, from which
+// the wave's window of touched small chunks follows (small_window).
+// Lanes past the end of a ragged batch load terms of the range too (their
+// indices are clamped), so every term noted belongs to the sum.  NoWin
+// notes nothing.
+struct NoWin {
+  template <int K>
+  __device__ __forceinline__ void note(const unsigned long long (&)[K]) {}
+};
+struct SmallWin {
+  unsigned int mn = 0xFFFFu, mx = 0u;
+  template <int K>
+  __device__ __forceinline__ void note(const unsigned long long (&t)[K]) {
+    unsigned int e[K];
+#pragma unroll
+    for (int j = 0; j < K; j++) e[j] = term_exp(t[j]);
+    const unsigned int a = umin_of(e), b = umax_of(e);
+    mn = mn < a ? mn : a;
+    mx = mx > b ? mx : b;
+  }
+};
+
 // Add one batch.  Lanes past hi in the last batch carry the term 0.
-template <class Src>
+template <class Src, class Win>
 __device__ __forceinline__ void small_batch_add(long long *mine, unsigned long long *spec, const Src &src,
                                                 const typename Src::Raw (&b)[kSmallU], long long base, long long hi,
-                                                int lane) {
-  unsigned long long t[kSmallU];
+                                                int lane, Win &w) {
+  unsigned long long t[kSmallU], u[kSmallU];
   const bool whole = base + 64 * kSmallU <= hi;
 #pragma unroll
   for (int j = 0; j < kSmallU; j++) {
-    t[j] = src.sterm(b[j]);
-    if (!whole && base + (long long)j * 64 + lane >= hi) t[j] = 0ull;
+    u[j] = src.sterm(b[j]);
+    t[j] = (!whole && base + (long long)j * 64 + lane >= hi) ? 0ull : u[j];
   }
+  w.note(u);
   small_terms_add(mine, spec, t);
 }
 
@@ -1287,28 +1320,33 @@ __device__ __forceinline__ void pair_batch_load_clamped(ulonglong2 (&v)[kPairV],
   }
   __builtin_amdgcn_sched_barrier(0);
 }
-template <class Src>
+template <class Src, class Win>
 __device__ __forceinline__ void pair_batch_add_whole(long long *mine, unsigned long long *spec, const Src &src,
-                                                     const ulonglong2 (&v)[kPairV]) {
+                                                     const ulonglong2 (&v)[kPairV], Win &w) {
   unsigned long long t[kSmallU];
 #pragma unroll
   for (int j = 0; j < kPairV; j++) {
     t[2 * j] = src.sterm(v[j].x);
     t[2 * j + 1] = src.sterm(v[j].y);
   }
+  w.note(t);
   small_terms_add(mine, spec, t);
 }
-template <class Src>
+template <class Src, class Win>
 __device__ __forceinline__ void pair_batch_add(long long *mine, unsigned long long *spec, const Src &src,
-                                               const ulonglong2 (&v)[kPairV], long long vb, long long nv, int lane) {
-  unsigned long long t[kSmallU];
+                                               const ulonglong2 (&v)[kPairV], long long vb, long long nv, int lane,
+                                               Win &w) {
+  unsigned long long t[kSmallU], u[kSmallU];
   const bool whole = vb + 64 * kPairV <= nv;
 #pragma unroll
   for (int j = 0; j < kPairV; j++) {
     const bool off = !whole && vb + (long long)j * 64 + lane >= nv;
-    t[2 * j] = off ? 0ull : src.sterm(v[j].x);
-    t[2 * j + 1] = off ? 0ull : src.sterm(v[j].y);
+    u[2 * j] = src.sterm(v[j].x);
+    u[2 * j + 1] = src.sterm(v[j].y);
+    t[2 * j] = off ? 0ull : u[2 * j];
+    t[2 * j + 1] = off ? 0ull : u[2 * j + 1];
   }
+  w.note(u);
   small_terms_add(mine, spec, t);
 }
 template <int COPIES>
@@ -1343,9 +1381,9 @@ __device__ __forceinline__ void pair_range_begin(PairRange<Src> &r, const Src &s
   r.fr = src.sload_nt(lane == 1 ? hi - 1 : lo);
   if (r.nv > 0) pair_batch_load_clamped(r.A, src, r.a, 0, r.nv, lane);
 }
-template <int COPIES, class Src>
+template <int COPIES, class Src, class Win = NoWin>
 __device__ __forceinline__ void pair_range_add(long long *acc, unsigned long long *spec, const Src &src,
-                                               PairRange<Src> &r, int lane) {
+                                               PairRange<Src> &r, int lane, Win &&w = Win{}) {
   constexpr int kEvery = 3 * COPIES;             // as in small_wave_accumulate
   constexpr long long kVB = 64 * kPairV;
   long long *mine = acc + copy_words<COPIES>() * (lane % COPIES);
@@ -1364,36 +1402,36 @@ __device__ __forceinline__ void pair_range_add(long long *acc, unsigned long lon
     // It always leaves the batch in hand in r.A.
     while (vb + 3 * kVB <= r.nv) {
       pair_batch_load_whole(B, src, r.a, vb + kVB, lane);
-      pair_batch_add_whole(mine, spec, src, r.A);
+      pair_batch_add_whole(mine, spec, src, r.A, w);
       tick();
       pair_batch_load_whole(r.A, src, r.a, vb + 2 * kVB, lane);
-      pair_batch_add_whole(mine, spec, src, B);
+      pair_batch_add_whole(mine, spec, src, B, w);
       tick();
       vb += 2 * kVB;
     }
     // r.A holds the batch at vb; at most two follow, the last maybe ragged.
     if (vb + kVB < r.nv) {
       pair_batch_load_clamped(B, src, r.a, vb + kVB, r.nv, lane);
-      pair_batch_add_whole(mine, spec, src, r.A);
+      pair_batch_add_whole(mine, spec, src, r.A, w);
       tick();
       vb += kVB;
       if (vb + kVB < r.nv) {
         pair_batch_load_clamped(r.A, src, r.a, vb + kVB, r.nv, lane);
-        pair_batch_add_whole(mine, spec, src, B);
+        pair_batch_add_whole(mine, spec, src, B, w);
         tick();
-        pair_batch_add(mine, spec, src, r.A, vb + kVB, r.nv, lane);
+        pair_batch_add(mine, spec, src, r.A, vb + kVB, r.nv, lane, w);
       } else {
-        pair_batch_add(mine, spec, src, B, vb, r.nv, lane);
+        pair_batch_add(mine, spec, src, B, vb, r.nv, lane, w);
       }
     } else {
-      pair_batch_add(mine, spec, src, r.A, vb, r.nv, lane);
+      pair_batch_add(mine, spec, src, r.A, vb, r.nv, lane, w);
     }
   }
-  // the edge terms: lanes 0 and 1 only (the others would add zeros)
-  if (r.fix) {
-    const unsigned long long ft[1] = {src.sterm(r.fr)};
-    small_terms_add(mine, spec, ft);
-  }
+  // the edge terms: lanes 0 and 1 only (the others would add zeros); every
+  // lane's edge load is a term of the range
+  const unsigned long long ft[1] = {src.sterm(r.fr)};
+  w.note(ft);
+  if (r.fix) small_terms_add(mine, spec, ft);
 }
 
 // The end of a wave's sum: carry steps of the copies (skipped when the range
@@ -1452,6 +1490,92 @@ __device__ __forceinline__ void small_wave_finish(long long *acc, int lane, bool
   __builtin_amdgcn_wave_barrier();
 }
 
+// The window of a wave's sum: small chunks [hb, hb + W) hold everything the
+// sum can occupy once the copies are added with the final carry folded in.
+// A term of exponent field e adds pieces to chunks e_eff >> 5 and the next,
+// and the fold moves high parts one chunk further, so the exponent range of
+// the terms bounds the window, provided no carry step ran on the way (each
+// moves high parts one chunk up): the range has at most win_max_terms
+// terms.  Returns false when the finish must cover every chunk: an infinity
+// or NaN among the terms (their side words are set), a window wider than
+// kWinRounds * 64 / COPIES chunks, or a longer range.  W = 0: no term.
+constexpr int kWinRounds = 2;
+template <int COPIES>
+constexpr long long win_max_terms() { return (3LL * COPIES - 1) * 64 * kSmallU; }
+
+template <int COPIES>
+__device__ __forceinline__ bool small_window(const SmallWin &w, long long n, int &hb, int &W) {
+  const unsigned int mn = wave_min_u32(w.mn), mx = wave_max_u32(w.mx);
+  hb = 0;
+  W = 0;
+  if (mn > mx) return true;                                  // no term
+  if (mx >= 2047u || n > win_max_terms<COPIES>()) return false;
+  hb = (int)((mn > 1u ? mn : 1u) >> 5);
+  W = (int)((mx > 1u ? mx : 1u) >> 5) + 3 - hb;
+  return W * COPIES <= 64 * kWinRounds;
+}
+
+// Sum over each group of COPIES consecutive lanes (8 or 16, within a row of
+// 16), left in every lane of the group: swap neighbours, swap pairs, mirror
+// the half-rows (and, for 16, the rows).
+template <int COPIES>
+__device__ __forceinline__ long long group_sum_i64(long long v) {
+  static_assert(COPIES == 8 || COPIES == 16, "group of 8 or 16 lanes");
+  unsigned long long u = (unsigned long long)v;
+  u += dpp_mov_u64<0xB1>(u);
+  u += dpp_mov_u64<0x4E>(u);
+  u += dpp_mov_u64<0x141>(u);
+  if (COPIES == 16) u += dpp_mov_u64<0x140>(u);
+  return (long long)u;
+}
+
+// small_wave_finish for a sum inside its window (small_window true; every
+// copy zero outside it): lane l reads copy l % COPIES of chunk hb + k G +
+// l / COPIES (G = 64 / COPIES chunks per round), the copies are added across
+// each lane group, and the first lane of the group writes the chunk's total
+// into the first copy while the others clear their words.  With the carry
+// folded in (skip_carry false), each word splits into its low 32 bits and
+// its high part as in small_wave_finish, and a chunk's total takes the high
+// sum of the chunk below (from the last lane of the group below: every lane
+// of a group holds its sums).  The top chunk of the window received no piece,
+// so no high part leaves it.  After it the first copy holds the sum (the
+// other copies are zero), each chunk below 2^37 in magnitude.
+template <int COPIES>
+__device__ __forceinline__ void small_wave_finish_window(long long *acc, int lane, bool skip_carry, int hb, int W) {
+  constexpr int G = 64 / COPIES;
+  const int c = lane % COPIES;
+  long long *mine = acc + copy_words<COPIES>() * c + hb;
+  unsigned long long below = 0ull;          // high sum of the chunk below the round's first
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int k = 0; k < kWinRounds; k++) {
+    if (k * G >= W) break;
+    const int r = k * G + lane / COPIES;
+    const bool valid = r < W;
+    long long v = 0;
+    if (valid) v = mine[r];
+    long long t;
+    if (skip_carry) {
+      t = group_sum_i64<COPIES>(v);
+    } else {
+      const long long lo = group_sum_i64<COPIES>(v & 0xFFFFFFFFll);
+      const long long hi = group_sum_i64<COPIES>(v >> 32);
+      t = lo + (long long)shr1_u64((unsigned long long)hi, below);
+      below = readlane_u64((unsigned long long)hi, 63);
+    }
+    if (valid) mine[r] = c == 0 ? t : 0ll;
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Clear the first copy's window after the sum was rounded (the rest of the
+// accumulator is zero already).
+__device__ __forceinline__ void small_window_clear(long long *acc, int lane, int hb, int W) {
+  __builtin_amdgcn_wave_barrier();
+  if (lane < W) acc[hb + lane] = 0;
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Wave adds the source's terms lo .. hi into acc (small_acc_words<COPIES>()
 // words, zeroed by the caller); specials into spec[3].  On return the sum is
 // in the first 68 words, each below COPIES * 2^33 in magnitude.  With
@@ -1462,6 +1586,15 @@ __device__ __forceinline__ void small_wave_finish(long long *acc, int lane, bool
 // With ZERO the accumulator is cleared here, after the first batch's loads
 // are issued, so that the clearing overlaps their latency (the caller then
 // need not zero it).
+template <bool ON>
+struct WinOf {
+  using T = NoWin;
+};
+template <>
+struct WinOf<true> {
+  using T = SmallWin;
+};
+
 template <int COPIES, class Src, bool ZERO = false>
 __device__ __forceinline__ void small_wave_accumulate(long long *acc, unsigned long long *spec, const Src &src,
                                                       long long lo, long long hi, int lane, bool direct = false) {
@@ -1470,6 +1603,8 @@ __device__ __forceinline__ void small_wave_accumulate(long long *acc, unsigned l
   // 1536 * 2^52 < 2^63
   constexpr int kEvery = 3 * COPIES;
   static_assert(64 % COPIES == 0 && kEvery * kSmallU * (64 / COPIES) <= 1536, "carry interval");
+  constexpr bool kWin = COPIES == 8 || COPIES == 16;     // windowed finish (group sums of 8 or 16 lanes)
+  typename WinOf<kWin>::T w;
   long long *mine = acc + copy_words<COPIES>() * (lane % COPIES);
   if (ZERO && !(hi > lo)) small_wave_zero<COPIES>(acc, spec, lane);
   if constexpr (Src::kPairs) {
@@ -1477,7 +1612,7 @@ __device__ __forceinline__ void small_wave_accumulate(long long *acc, unsigned l
       PairRange<Src> r;
       pair_range_begin(r, src, lo, hi, lane);
       if (ZERO) small_wave_zero<COPIES>(acc, spec, lane);
-      pair_range_add<COPIES>(acc, spec, src, r, lane);
+      pair_range_add<COPIES>(acc, spec, src, r, lane, w);
     }
   } else if (hi > lo) {
     constexpr long long kB = 64 * kSmallU;
@@ -1487,7 +1622,7 @@ __device__ __forceinline__ void small_wave_accumulate(long long *acc, unsigned l
     int batches = 0;
     for (long long base = lo;;) {
       small_batch_load(B, src, base + kB, hi, lane);
-      small_batch_add(mine, spec, src, A, base, hi, lane);
+      small_batch_add(mine, spec, src, A, base, hi, lane, w);
       base += kB;
       if (++batches == kEvery) {
         batches = 0;
@@ -1495,13 +1630,20 @@ __device__ __forceinline__ void small_wave_accumulate(long long *acc, unsigned l
       }
       if (base >= hi) break;
       small_batch_load(A, src, base + kB, hi, lane);
-      small_batch_add(mine, spec, src, B, base, hi, lane);
+      small_batch_add(mine, spec, src, B, base, hi, lane, w);
       base += kB;
       if (++batches == kEvery) {
         batches = 0;
         small_carry_all<COPIES>(acc, lane);
       }
       if (base >= hi) break;
+    }
+  }
+  if constexpr (kWin) {
+    int hb, W;
+    if (small_window<COPIES>(w, hi - lo, hb, W)) {
+      small_wave_finish_window<COPIES>(acc, lane, direct && hi - lo < 1024, hb, W);
+      return;
     }
   }
   small_wave_finish<COPIES>(acc, lane, direct && hi - lo < 1024);

@@ -90,6 +90,36 @@ __device__ __forceinline__ long long wave_sum_i64(long long v) {
   return (long long)wave_sum_u64((unsigned long long)v);
 }
 
+// Minimum and maximum over the 64 lanes, the same way (wave-uniform).
+__device__ __forceinline__ unsigned int wave_min_u32(unsigned int v) {
+  unsigned int u;
+  u = (unsigned int)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false); v = v < u ? v : u;
+  u = (unsigned int)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false); v = v < u ? v : u;
+  u = (unsigned int)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, false); v = v < u ? v : u;
+  u = (unsigned int)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, false); v = v < u ? v : u;
+  unsigned int m = (unsigned int)__builtin_amdgcn_readlane((int)v, 0);
+#pragma unroll
+  for (int r = 16; r < 64; r += 16) {
+    const unsigned int x = (unsigned int)__builtin_amdgcn_readlane((int)v, r);
+    m = m < x ? m : x;
+  }
+  return m;
+}
+__device__ __forceinline__ unsigned int wave_max_u32(unsigned int v) {
+  unsigned int u;
+  u = (unsigned int)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false); v = v > u ? v : u;
+  u = (unsigned int)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false); v = v > u ? v : u;
+  u = (unsigned int)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, false); v = v > u ? v : u;
+  u = (unsigned int)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, false); v = v > u ? v : u;
+  unsigned int m = (unsigned int)__builtin_amdgcn_readlane((int)v, 0);
+#pragma unroll
+  for (int r = 16; r < 64; r += 16) {
+    const unsigned int x = (unsigned int)__builtin_amdgcn_readlane((int)v, r);
+    m = m > x ? m : x;
+  }
+  return m;
+}
+
 // ---- large chunk -> three small-chunk pieces -------------------------------
 
 // Chunk index ix (sign<<11 | exponent field), raw-pattern sum C of k adds.

@@ -383,15 +383,20 @@ __global__ __launch_bounds__(BLOCK) void seg_short_kernel(const double *__restri
     if (have && b > a) pair_range_begin(R, src, a, b, lane);
     small_wave_zero<kShortCopies>(acc, spec, lane);
     while (have) {
-      if (b > a) pair_range_add<kShortCopies>(acc, spec, src, R, lane);
+      SmallWin w;
+      if (b > a) pair_range_add<kShortCopies>(acc, spec, src, R, lane, w);
       int j1 = 0;
       long long a1 = 0, b1 = 0;
       const bool next = claim(j1, a1, b1);
       if (next && b1 > a1) pair_range_begin(R, src, a1, b1, lane);
-      small_wave_finish<kShortCopies>(acc, lane, b - a < 1024);
+      int hb, W;
+      const bool win = small_window<kShortCopies>(w, b - a, hb, W);
+      if (win) small_wave_finish_window<kShortCopies>(acc, lane, b - a < 1024, hb, W);
+      else small_wave_finish<kShortCopies>(acc, lane, b - a < 1024);
       wave_merge_and_round(acc, spec, nullptr, 1u, &out[r0 + j], lane);
       if (!next) break;
-      small_wave_zero<kShortCopies>(acc, spec, lane);
+      if (win) small_window_clear(acc, lane, hb, W);
+      else small_wave_zero<kShortCopies>(acc, spec, lane);
       j = j1;
       a = a1;
       b = b1;

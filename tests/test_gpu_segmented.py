@@ -271,3 +271,85 @@ def test_small_body_top_chunks(ex):
             ex.exsum_f64(dev(p), out=out)
             torch.cuda.synchronize()
             assert int(out.cpu().numpy().view(np.uint64)[0]) == int(oracle.sum_f64(p)), (k, p.size)
+
+
+def test_small_window_edges(ex):
+    """The small body's windowed finish: a sum whose terms' exponent fields
+    span few small chunks adds only the copies' words of that window, and
+    the accumulator must be clear everywhere else for the next sum.  Each
+    class of values below hits one case of the window: 3, 4, 5 and 8 chunks
+    (one round of lane groups, a partial second round, two full rounds, the
+    limit with 16 copies), 9 and 18 chunks (the full finish with 16 copies;
+    9 is still a window with 8), the top chunks (up to overflow), denormals
+    (window from chunk 0), zeros (full finish), an infinity or NaN (full
+    finish, side words cleared), exact cancellation, and rounding ties.
+    Lengths cover edge-only ranges, ragged batches, the 1024-term boundary
+    of the direct sum without carries and the longest range the window
+    takes without carry steps (24,064 terms with 16 copies).  The segments
+    are shuffled so that windowed and full finishes follow each other on
+    the same wavefront; every result against the oracle, as segments, as
+    single sums and as dot products."""
+    rng = np.random.default_rng(23)
+
+    def vals(n, e0, e1, sign=True):
+        m = rng.integers(0, 1 << 52, n, dtype=np.uint64)
+        e = rng.integers(e0, e1 + 1, n).astype(np.uint64)
+        s = (rng.integers(0, 2, n).astype(np.uint64) << np.uint64(63)) if sign else np.uint64(0)
+        return ((e << np.uint64(52)) | m | s).view(np.float64)
+
+    classes = {
+        "w3": (1024, 1055), "w4": (992, 1055), "w5": (960, 1055), "w8": (864, 1055),
+        "w9": (832, 1055), "w18": (544, 1055), "top": (2016, 2046), "top2": (1984, 2046),
+        "denorm": (0, 40),
+    }
+    parts = []
+    for name, (e0, e1) in classes.items():
+        for n in (1, 2, 3, 5, 64, 129, 511, 513, 1023, 1024, 1025, 2047, 4096, 12288):
+            parts.append(vals(n, e0, e1))
+        parts.append(vals(3000, e0, e1, sign=False))
+    for n in (3, 1024, 5000):
+        z = vals(n, 1024, 1055)
+        z[rng.integers(0, n, max(1, n // 100))] = 0.0
+        parts.append(z)
+        sp = vals(n, 992, 1055)
+        sp[rng.integers(0, n)] = [np.inf, -np.inf, np.nan][n % 3]
+        parts.append(sp)
+        h = vals(n, 960, 1055)
+        pair = np.empty(2 * n)
+        pair[0::2], pair[1::2] = h, -h
+        parts.append(rng.permutation(pair))
+    tie = np.ldexp(1.0, -53)
+    one_up = 1.0 + np.ldexp(1.0, -52)
+    for s in (1.0, -1.0):
+        parts += [s * np.array([1.0, tie]), s * np.array([1.0, tie, np.ldexp(1.0, -100)]),
+                  s * np.array([one_up, tie]), s * np.array([tie, 1.0, -np.ldexp(1.0, -100)])]
+    # the longest windowed range, all terms on one chunk at full significand
+    # (copy words near 2^62.5), and just past it
+    for n in (24063, 24064, 24065):
+        parts.append(np.full(n, np.ldexp(2.0 - 2.0 ** -52, 31)))
+        parts.append(vals(n, 960, 1055))
+    order = rng.permutation(len(parts))
+    parts = [parts[i] for i in order]
+    lens = [p.size for p in parts]
+    x = np.concatenate(parts)
+    off = np.zeros(len(lens) + 1, dtype=np.int64)
+    np.cumsum(lens, out=off[1:])
+    want = oracle.segmented_f64(x, off)
+    xt, offt = dev(x), dev(off)
+    for sm in (12288, 65536):
+        for mode in (0, 1):
+            got = seg_bits(ex, xt, offt, seg_small_max=sm, seg_mode=mode)
+            bad = np.nonzero(got != want)[0]
+            assert bad.size == 0, (sm, mode, bad[:5], [lens[i] for i in bad[:5]])
+    out = torch.empty(1, dtype=torch.float64, device="cuda:0")
+    two = np.ldexp(np.ones(4096), rng.integers(-3, 4, 4096))
+    for k, p in enumerate(parts):
+        if p.size <= 4096:
+            ex.exsum_f64(dev(p), out=out)
+            torch.cuda.synchronize()
+            assert int(out.cpu().numpy().view(np.uint64)[0]) == int(oracle.sum_f64(p)), (k, p.size)
+            if p.size >= 64 and k % 3 == 0:
+                y = two[:p.size]
+                ex.exsum_dot_f64(dev(p), dev(y), out=out)
+                torch.cuda.synchronize()
+                assert int(out.cpu().numpy().view(np.uint64)[0]) == int(oracle.dot_f64(p, y)), (k, p.size)
