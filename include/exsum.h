@@ -172,11 +172,15 @@ int exsum_inexact_f64(const double *x, int64_t n, double *out, void *stream);
  *                 interleaved table copies serve a shared chunk better.)
  *   small_max   : inputs with n <= small_max use the small-only kernel.
  *   small_grid  : workgroups of the small-only kernel; 0 = automatic.
- *   seg_grid    : workgroups of the segmented call's long-segment kernel
- *                 (the batch's terms split evenly over them, at most 8192);
- *                 0 = twelve per compute unit, of which three fit at once,
- *                 so that compute units whose ranges hold fewer long
- *                 segments take more ranges.
+ *   seg_grid    : workgroups of the segmented call's long-segment kernel,
+ *                 one term range each, at most 8192.  The batch's terms are
+ *                 split into ranges that shrink along the dispatch order,
+ *                 from 1.8 to 0.2 times the mean, when the batch has enough
+ *                 terms for every range to stay nonempty (N (G - 4) >= 5 G^2);
+ *                 otherwise evenly.  0 = twelve per compute unit, of which
+ *                 three fit at once, so that compute units whose ranges hold
+ *                 fewer long segments take more ranges, and the ranges
+ *                 started last are short.
  *   seg_small_max : segments of at most this many terms (0 .. 2^20) are
  *                   summed by one wavefront with the small accumulator
  *                   alone; longer ones by workgroups with the large one.

@@ -2,18 +2,19 @@
 // on the caller's stream that write disjoint outputs.
 //
 // Long segments (more than small_max terms) are summed first, by workgroups
-// with the large accumulator (carry mode).  Workgroup w of G takes the terms
-// [o0 + N*w/G, o0 + N*(w+1)/G) (N = offsets[nseg] - offsets[0]; G is the
-// grid capped at N, so that no range is empty), so every workgroup reads the
-// same number of bytes of the concatenated input whatever the lengths.  It
+// with the large accumulator (carry mode).  Workgroup w of G takes term range
+// w of the concatenated input (N = offsets[nseg] - offsets[0] terms): the
+// ranges split the terms whatever the lengths, shrinking along the dispatch
+// order when N is large enough (RangeSplit), evenly otherwise.  A workgroup
 // finds the segment holding its first term with a wavefront-wide search of
 // the offsets and walks the long segments that meet its range in batches of
 // up to 256.  A segment inside one range is rounded by that workgroup; a
 // segment cut by range boundaries adds its pieces into the accumulator slot
-// of the first workgroup that holds one, a ticket counts the pieces (exactly
-// the workgroups wg_of(first) .. wg_of(last)), and the piece that completes
-// the count rounds.  The same launch also sums the weights of the short
-// kernel's chunks of segments, from which that kernel partitions its work.
+// of the first range that holds one, a ticket counts the pieces (exactly
+// the ranges range_of(first) .. range_of(last)), and the piece that
+// completes the count rounds.  The same launch also sums the weights of the
+// short kernel's chunks of segments, from which that kernel partitions its
+// work.
 //
 // Short segments (at most small_max terms, empty ones included) are then
 // summed whole by single wavefronts with the small-superaccumulator body and
@@ -36,10 +37,60 @@ constexpr int kSegBatch = 256;
 // each segment.
 constexpr long long kSegCost = 2048;
 
-// Workgroup of G whose term range contains relative position p (0 <= p < N):
-// the largest w with floor(N*w/G) <= p.
-__device__ __forceinline__ long long wg_of(long long p, long long N, long long G) {
-  return ((p + 1) * G + N - 1) / N - 1;
+// The long-segment kernel's term ranges: range w of G is [o0 + B(w),
+// o0 + B(w + 1)) with B(w) = floor(N f(w) / D), f(w) = w (5G + A (G - w)),
+// D = 5 G^2, so B(0) = 0 and B(G) = N.  With A = 0 the ranges are equal;
+// with A = 4 they shrink along the dispatch order from 1.8 N/G to 0.2 N/G,
+// so that the ranges started last, when the chip drains, are short (a
+// workgroup streams at a bounded rate, and a long range started late sets
+// the end of the launch).  A = 4 is taken when N ((5 - A) G - A) >= D, which
+// keeps every range nonempty (f rises by at least (5 - A) G - A per step, so
+// B by more than N ((5 - A) G - A) / D - 1 >= 0); otherwise A = 0 and G <= N.  B is evaluated as q f + floor(r f / D) with
+// N = q D + r, exact and without overflow for N < 2^62 and G <= 8192.
+struct RangeSplit {
+  long long N, G, D, q, r;
+  int A;
+  __device__ __forceinline__ long long B(long long w) const {
+    const long long f = w * (5 * G + A * (G - w));
+    // floor(r f / D) from a binary64 estimate, corrected exactly (no 64-bit
+    // division; r f < 2^58, so the estimate is off by a few units at most)
+    const long long rf = r * f;
+    long long t = (long long)((double)rf / (double)D);
+    long long m = rf - t * D;
+    while (m < 0) { t--; m += D; }
+    while (m >= D) { t++; m -= D; }
+    return q * f + t;
+  }
+  // The range holding relative position p (0 <= p < N): the largest w with
+  // B(w) <= p, from the inverse of the quadratic, corrected exactly.
+  __device__ __forceinline__ long long range_of(long long p) const {
+    const double x = ((double)p + 0.5) / (double)N;
+    double t = x;
+    if (A) {
+      const double a = A / 5.0;
+      t = ((1.0 + a) - sqrt((1.0 + a) * (1.0 + a) - 4.0 * a * x)) / (2.0 * a);
+    }
+    long long w = (long long)(t * (double)G);
+    w = w < 0 ? 0 : (w > G - 1 ? G - 1 : w);
+    while (w > 0 && B(w) > p) w--;
+    while (w + 1 < G && B(w + 1) <= p) w++;
+    return w;
+  }
+};
+__device__ __forceinline__ RangeSplit range_split(long long N, long long grid, bool guided) {
+  RangeSplit R;
+  R.N = N;
+  R.A = 0;
+  R.G = grid < N ? grid : N;
+  // N (G - 4) >= 5 G^2, as N >= ceil(5 G^2 / (G - 4)) (no overflow)
+  if (guided && grid > 4 && N >= (5 * grid * grid + grid - 5) / (grid - 4)) {
+    R.A = 4;
+    R.G = grid;
+  }
+  R.D = 5 * R.G * R.G;
+  R.q = N / R.D;
+  R.r = N % R.D;
+  return R;
 }
 
 struct SegShared {
@@ -47,6 +98,7 @@ struct SegShared {
   long long off[kSegBatch + 1];        // a batch of segment offsets
   unsigned int nb;                     // segments of this batch that meet the range
   long long first;                     // first segment of the range
+  long long split[6];                  // the term split (RangeSplit), read back where needed
   long long red[16];                   // wave partial sums
 };
 
@@ -61,19 +113,28 @@ template <int BLOCK, int VEC, int DEPTH>
 __device__ __forceinline__ void long_phase(SegShared &S, const double *__restrict__ x,
                                            const long long *__restrict__ offsets, long long nseg,
                                            double *__restrict__ out, GlobalAcc *__restrict__ accs,
-                                           long long small_max, int precombine) {
+                                           long long small_max, int precombine, bool guided) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // all lanes active here
   const long long o0 = offsets[0], oN = offsets[nseg];
   const long long N = oN - o0;
   if (N <= 0) return;                                   // no terms: only empty (short) segments
-  // at most one workgroup per term, so every range is nonempty and a
-  // segment's pieces are exactly the workgroups wg_of(first) .. wg_of(last)
-  const long long G = ((long long)gridDim.x < N) ? (long long)gridDim.x : N;
-  const long long w = blockIdx.x;
-  if (w >= G) return;                                   // whole workgroup, before any barrier
+  // every range is nonempty, so a segment's pieces are exactly the ranges
+  // range_of(first) .. range_of(last)
+  long long lo_w, hi_w;
+  {
+    const RangeSplit RS = range_split(N, (long long)gridDim.x, guided);
+    const long long w = blockIdx.x;
+    if (w >= RS.G) return;                              // whole workgroup, before any barrier
+    lo_w = o0 + RS.B(w);
+    hi_w = o0 + RS.B(w + 1);
+    // kept in LDS, not in registers through the streaming loop
+    if (tid == 0) {
+      S.split[0] = RS.N; S.split[1] = RS.G; S.split[2] = RS.D;
+      S.split[3] = RS.q; S.split[4] = RS.r; S.split[5] = RS.A;
+    }
+  }
   large_init(S.L, tid, BLOCK);
-  const long long lo_w = o0 + N * w / G, hi_w = o0 + N * (w + 1) / G;
 
   // first segment: i = j - 1 for the smallest j in [1, nseg] with
   // offsets[j] > lo_w, the segment that holds term lo_w (offsets[nseg] > lo_w
@@ -138,8 +199,15 @@ __device__ __forceinline__ void long_phase(SegShared &S, const double *__restric
       unsigned int expected = 1;
       GlobalAcc *g = nullptr;
       if (split) {
-        const long long w1 = wg_of(s0 - o0, N, G);
-        expected = (unsigned int)(wg_of(s1 - 1 - o0, N, G) - w1 + 1);
+        // the ranges of the segment's first and last terms (this range's own
+        // index where the segment starts or ends in it)
+        RangeSplit RS;
+        RS.N = uniform_i64(S.split[0]); RS.G = uniform_i64(S.split[1]); RS.D = uniform_i64(S.split[2]);
+        RS.q = uniform_i64(S.split[3]); RS.r = uniform_i64(S.split[4]); RS.A = (int)uniform_i64(S.split[5]);
+        const long long w = blockIdx.x;
+        const long long w1 = s0 >= lo_w ? w : RS.range_of(s0 - o0);
+        const long long wl = s1 <= hi_w ? w : RS.range_of(s1 - 1 - o0);
+        expected = (unsigned int)(wl - w1 + 1);
         g = &accs[w1];
       }
       merge_and_round(S.L.small, S.L.spec, &S.L.ticket, g, expected, &out[i + k]);
@@ -183,7 +251,7 @@ __global__ __launch_bounds__(BLOCK) void seg_long_kernel(const double *__restric
       __syncthreads();
     }
   }
-  long_phase<BLOCK, VEC, DEPTH>(S, x, offsets, nseg, out, accs, small_max, precombine);
+  long_phase<BLOCK, VEC, DEPTH>(S, x, offsets, nseg, out, accs, small_max, precombine, true);
 }
 
 constexpr int kShortCopies = 16;
@@ -535,7 +603,7 @@ void seg_persistent_kernel(const double *__restrict__ x, const long long *__rest
   __shared__ PersistShared<NW> U;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // all lanes active here
-  long_phase<BLOCK, VEC, DEPTH>(U.L, x, offsets, nseg, out, accs, small_max, precombine);
+  long_phase<BLOCK, VEC, DEPTH>(U.L, x, offsets, nseg, out, accs, small_max, precombine, false);
   __syncthreads();                                    // the long phase's LDS is reused below
 
   long long *acc = U.S.acc[wave];

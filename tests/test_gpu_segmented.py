@@ -353,3 +353,33 @@ def test_small_window_edges(ex):
                 ex.exsum_dot_f64(dev(p), dev(y), out=out)
                 torch.cuda.synchronize()
                 assert int(out.cpu().numpy().view(np.uint64)[0]) == int(oracle.dot_f64(p, y)), (k, p.size)
+
+
+def test_long_range_split_edges(ex):
+    """The long-segment kernel's term ranges shrink along the dispatch order
+    (range w of G starts at floor(N f(w) / 5G^2), f(w) = w (5G + 4(G - w)))
+    once N (G - 4) >= 5 G^2, and are equal otherwise (G capped at N).  Batches
+    of N terms just below, at and above that bound for several grids, made of
+    segments longer than the small/large threshold so that many are cut into
+    pieces over several ranges (merged by ticket), and larger batches; every
+    result against the oracle, with the grid and threshold varied."""
+    rng = np.random.default_rng(29)
+    for G in (5, 6, 37, 64, 300):
+        bound = -(-5 * G * G // (G - 4))          # smallest N with N (G - 4) >= 5 G^2
+        for N in sorted({bound - 1, bound, bound + 1, 5 * G + 3, 40 * G + 7}):
+            if N < 1:
+                continue
+            lens = []
+            left = N
+            while left > 0:
+                k = int(min(left, rng.integers(1, 3 * max(1, N // G) + 2)))
+                lens.append(k)
+                left -= k
+            x = np.ldexp(rng.uniform(1, 2, N), rng.integers(-40, 40, N)) * rng.choice([-1.0, 1.0], N)
+            off = np.zeros(len(lens) + 1, dtype=np.int64)
+            np.cumsum(lens, out=off[1:])
+            want = oracle.segmented_f64(x, off)
+            xt, offt = dev(x), dev(off)
+            for sm in (0, 2, 16):
+                got = seg_bits(ex, xt, offt, seg_grid=G, seg_small_max=sm, seg_mode=0)
+                assert np.array_equal(got, want), (G, N, sm)
