@@ -177,7 +177,7 @@ int exsum_inexact_f64(const double *x, int64_t n, double *out, void *stream);
  *                 split into ranges that shrink along the dispatch order,
  *                 from 1.8 to 0.2 times the mean, when the batch has enough
  *                 terms for every range to stay nonempty (N (G - 4) >= 5 G^2);
- *                 otherwise evenly.  0 = twelve per compute unit, of which
+ *                 otherwise evenly.  0 = eight per compute unit, of which
  *                 three fit at once, so that compute units whose ranges hold
  *                 fewer long segments take more ranges, and the ranges
  *                 started last are short.

@@ -287,10 +287,10 @@ int exsum_segmented_f64(const double *x, const int64_t *offsets, int64_t nseg, d
                                                  c.seg_small_max, c.precombine, c.seg_group));
   }
   int grid = c.seg_grid;
-  // long segments: twelve workgroups per compute unit (three fit at once),
-  // so that the dispatcher hands more of the evenly split term ranges to
+  // long segments: eight workgroups (term ranges) per compute unit, three
+  // of which fit at once, so that the dispatcher hands more ranges to
   // compute units whose ranges hold fewer long segments
-  if (grid == 0) grid = std::min(12 * cu_count(dev), kMaxGrid);
+  if (grid == 0) grid = std::min(8 * cu_count(dev), kMaxGrid);
   // short segments: one workgroup per compute unit
   const int short_grid = std::min(cu_count(dev), seg_short_block());
   return status_of(launch_segmented(x, offsets, nseg, out, accs, chunks, s, grid, short_grid, c.seg_small_max,
