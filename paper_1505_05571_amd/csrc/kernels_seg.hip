@@ -32,10 +32,10 @@ namespace exsum {
 namespace {
 
 constexpr int kSegBatch = 256;
-// Cost of one short segment beyond its terms (zeroing, rounding, the first
-// load's latency), in terms: the weight the short kernel's partition gives
-// each segment.
-constexpr long long kSegCost = 2048;
+// Cost of one short segment beyond its terms (the finish over its window,
+// rounding, the first load's latency), in terms: the weight the short
+// kernel's partition gives each segment.
+constexpr long long kSegCost = 1024;
 
 // The long-segment kernel's term ranges: range w of G is [o0 + B(w),
 // o0 + B(w + 1)) with B(w) = floor(N f(w) / D), f(w) = w (5G + A (G - w)),
