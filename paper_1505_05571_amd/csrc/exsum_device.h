@@ -181,11 +181,18 @@ __device__ __forceinline__ unsigned int term_exp(unsigned long long b) {
 __device__ __forceinline__ void term_pieces_e(unsigned long long b, unsigned int e, int &h, long long &plo,
                                               long long &phi) {
   const unsigned int e_eff = e > 1u ? e : 1u;
-  const unsigned int hidden = e < 1u ? e : 1u;                       // 0 for a denormal
+  // min(e, 1) (0 for a denormal) and e_eff >> 5 as single instructions: the
+  // compiler would turn the first into a compare and select and fold the
+  // second into the LDS address as a shift and mask; this way the hidden bit
+  // joins the significand with one shift-or and the address is one
+  // shift-add
+  unsigned int hidden, hh;
+  asm("v_min_u32 %0, 1, %1" : "=v"(hidden) : "v"(e));
+  asm("v_bfe_u32 %0, %1, 5, 6" : "=v"(hh) : "v"(e_eff));
   const unsigned int mhi = (hidden << 20) | ((unsigned int)(b >> 32) & 0xFFFFFu);
   const unsigned long long M = ((unsigned long long)mhi << 32) | (unsigned int)b;
   const unsigned int lo = e_eff & 31u;
-  h = (int)__builtin_amdgcn_ubfe(e_eff, 5u, 6u);
+  h = (int)hh;
   const long long neg = (long long)b >> 63;          // 0 or -1
   const long long Ms = (long long)((M ^ (unsigned long long)neg) - (unsigned long long)neg);
   plo = (long long)(unsigned int)((unsigned int)(unsigned long long)Ms << lo);
