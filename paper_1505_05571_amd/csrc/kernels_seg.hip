@@ -45,8 +45,9 @@ constexpr long long kSegCost = 1024;
 // workgroup streams at a bounded rate, and a long range started late sets
 // the end of the launch).  A = 4 is taken when N ((5 - A) G - A) >= D, which
 // keeps every range nonempty (f rises by at least (5 - A) G - A per step, so
-// B by more than N ((5 - A) G - A) / D - 1 >= 0); otherwise A = 0 and G <= N.  B is evaluated as q f + floor(r f / D) with
-// N = q D + r, exact and without overflow for N < 2^62 and G <= 8192.
+// B by more than N ((5 - A) G - A) / D - 1 >= 0); otherwise A = 0 and
+// G <= N.  B is evaluated as q f + floor(r f / D) with N = q D + r, exact and
+// without overflow for N < 2^62 and G <= 8192 (r f < 2^58).
 struct RangeSplit {
   long long N, G, D, q, r;
   int A;
