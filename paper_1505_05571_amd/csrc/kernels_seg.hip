@@ -299,7 +299,8 @@ struct ShortShared {
   int ccount[3][BLOCK / 64];
   int cnt;                             // 64 x the next entry of ord to hand out
   long long red[BLOCK / 64];
-  long long first;
+  int kk[2];                           // the chunks holding the range's two ends
+  unsigned long long f[2];             // the range's two ends
 };
 
 // Weight of segment i in the partition of the short kernel's work.
@@ -309,46 +310,63 @@ __device__ __forceinline__ long long seg_weight(const long long *__restrict__ of
   return len <= small_max ? len + kSegCost : 0;
 }
 
-// First segment of the short kernel's workgroup range that starts at weight
-// position `target`: the smallest i whose exclusive weight prefix is at
-// least target, or nseg.  Chunk k holds segments [k*nseg/C, (k+1)*nseg/C)
-// and chunks[k] their total weight.  Called by every thread.
+// Both ends of workgroup g's range of G in the weight partition, in one pass
+// (every chunk of segments holds at most BLOCK of them): range g starts at
+// the first segment whose exclusive weight prefix reaches ceil(g T / G) (T
+// the total weight) and ends where range g + 1 starts (the last one at
+// nseg).  Chunk k holds segments [k*nseg/C, (k+1)*nseg/C) and chunks[k]
+// their total weight.  The chunk weights are scanned once, the chunks that
+// hold the two targets are found together, both chunks' segment weights are
+// loaded at once, and two block scans give, in each chunk, the first
+// segment whose prefix reaches its target (the chunk's end if none).  Each
+// end is computed the same way by both workgroups it separates, so every
+// segment belongs to exactly one range.  Returns T (0: no short segments,
+// and g0, g1 unset).  Called by every thread.
 template <int BLOCK>
-__device__ long long short_range_start(const long long *__restrict__ offsets, long long nseg, long long small_max,
-                                       const long long *__restrict__ chunks, int C, long long target,
-                                       ShortShared<BLOCK> &S) {
+__device__ __forceinline__ long long short_range_pair(const long long *__restrict__ offsets, long long nseg,
+                                                      long long small_max, const long long *__restrict__ chunks,
+                                                      int C, long long g, long long G, ShortShared<BLOCK> &S,
+                                                      long long &g0, long long &g1) {
   const int tid = threadIdx.x;
-  // chunk prefix sums (C <= BLOCK): lo[k] = weight before chunk k
-  long long tot = 0;
+  long long T = 0;
   const long long wk = tid < C ? chunks[tid] : 0;
-  const long long inc = block_incl_scan<BLOCK>(wk, S.red, tot);
+  const long long inc = block_incl_scan<BLOCK>(wk, S.red, T);
+  if (T == 0) return 0;
+  S.lo[tid] = inc - wk;                               // weight before chunk tid
+  if (tid < 2) S.kk[tid] = 0;
   __syncthreads();
-  S.lo[tid] = inc - wk;
-  if (tid == 0) S.first = 0;
-  __syncthreads();
-  // the last chunk starting at or before target
-  const unsigned long long m = __ballot(tid < C && S.lo[tid] <= target);
-  if ((tid & 63) == 0 && m) atomicMax((unsigned long long *)&S.first, (unsigned long long)(tid + 63 - __clzll(m)));
-  __syncthreads();
-  const long long k = uniform_i64(S.first);
-  long long base = uniform_i64(S.lo[k]);
-  const long long c0 = k * nseg / C, c1 = (k + 1) * nseg / C;
-  __syncthreads();
-  if (tid == 0) S.first = c1;
-  __syncthreads();
-  for (long long r = c0; r < c1; r += BLOCK) {
-    const long long i = r + tid;
-    const long long w = i < c1 ? seg_weight(offsets, i, small_max) : 0;
-    long long step = 0;
-    const long long e = base + block_incl_scan<BLOCK>(w, S.red, step) - w;
-    if (i < c1 && e >= target) atomicMin((unsigned long long *)&S.first, (unsigned long long)i);
-    base += step;
-    __syncthreads();
-    if (uniform_i64(S.first) < c1) break;
+  const bool has1 = g + 1 < G;
+  const long long t0 = (g * T + G - 1) / G;
+  const long long t1 = has1 ? ((g + 1) * T + G - 1) / G : T;
+  // the last chunk whose prefix is at most each target (chunk 0's is 0)
+  const unsigned long long m0 = __ballot(tid < C && S.lo[tid] <= t0);
+  const unsigned long long m1 = __ballot(tid < C && S.lo[tid] <= t1);
+  if ((tid & 63) == 0) {
+    if (m0) atomicMax(&S.kk[0], tid + 63 - __clzll(m0));
+    if (m1) atomicMax(&S.kk[1], tid + 63 - __clzll(m1));
   }
-  const long long f = uniform_i64(S.first);
   __syncthreads();
-  return f;
+  const long long k0 = __builtin_amdgcn_readfirstlane(S.kk[0]), k1 = __builtin_amdgcn_readfirstlane(S.kk[1]);
+  const long long base0 = uniform_i64(S.lo[k0]), base1 = uniform_i64(S.lo[k1]);
+  const long long a0 = k0 * nseg / C, b0 = (k0 + 1) * nseg / C;
+  const long long a1 = k1 * nseg / C, b1 = (k1 + 1) * nseg / C;
+  const long long i0 = a0 + tid, i1 = a1 + tid;
+  const long long w0 = i0 < b0 ? seg_weight(offsets, i0, small_max) : 0;
+  const long long w1 = (has1 && i1 < b1) ? seg_weight(offsets, i1, small_max) : 0;
+  if (tid == 0) {
+    S.f[0] = (unsigned long long)b0;
+    S.f[1] = (unsigned long long)b1;
+  }
+  long long step = 0;
+  const long long e0 = base0 + block_incl_scan<BLOCK>(w0, S.red, step) - w0;
+  if (i0 < b0 && e0 >= t0) atomicMin(&S.f[0], (unsigned long long)i0);
+  const long long e1 = base1 + block_incl_scan<BLOCK>(w1, S.red, step) - w1;
+  if (has1 && i1 < b1 && e1 >= t1) atomicMin(&S.f[1], (unsigned long long)i1);
+  __syncthreads();
+  g0 = uniform_i64((long long)S.f[0]);
+  g1 = has1 ? uniform_i64((long long)S.f[1]) : nseg;
+  __syncthreads();
+  return T;
 }
 
 // Short segments (at most small_max terms, empty ones included).  Workgroup
@@ -373,17 +391,8 @@ __global__ __launch_bounds__(BLOCK) void seg_short_kernel(const double *__restri
   const long long G = gridDim.x, g = blockIdx.x;
   long long g0, g1;
   if (plan) {
-    const int C = (int)G;
-    long long T = 0;
-    {
-      const long long wk = tid < C ? chunks[tid] : 0;
-      (void)block_incl_scan<BLOCK>(wk, S.red, T);
-      __syncthreads();
-    }
-    if (T == 0) return;                                 // no short segments
-    g0 = short_range_start<BLOCK>(offsets, nseg, small_max, chunks, C, (g * T + G - 1) / G, S);
-    g1 = nseg;
-    if (g + 1 < G) g1 = short_range_start<BLOCK>(offsets, nseg, small_max, chunks, C, ((g + 1) * T + G - 1) / G, S);
+    if (short_range_pair<BLOCK>(offsets, nseg, small_max, chunks, (int)G, g, G, S, g0, g1) == 0)
+      return;                                           // no short segments
   } else {
     g0 = nseg * g / G;
     g1 = nseg * (g + 1) / G;
