@@ -54,7 +54,7 @@ exsum_config default_config() {
   c.small_max = 4096;
   c.small_grid = 0;
   c.seg_grid = 0;
-  c.seg_small_max = 12288;
+  c.seg_small_max = 20480;
   c.seg_mode = 0;
   c.seg_block = 256;
   c.seg_group = 8;

@@ -385,7 +385,7 @@ int autotune_body(const char *cache_path, std::string &js, std::string &err, voi
     }
     if ((st = gen(n_seg, 2, 13)) != EXSUM_OK) return fail(st, "generating an input");
     std::vector<exsum_config> sc;
-    for (int64_t sm : {8192, 12288, 16384})
+    for (int64_t sm : {12288, 16384, 20480})
       for (int g : {0, 6 * id.cus, 12 * id.cus}) {
         exsum_config c = best;
         c.seg_mode = 0;
