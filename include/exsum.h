@@ -183,13 +183,15 @@ int exsum_inexact_f64(const double *x, int64_t n, double *out, void *stream);
  *                 started last are short.
  *   seg_small_max : segments of at most this many terms (0 .. 2^20) are
  *                   summed by one wavefront with the small accumulator
- *                   alone; longer ones by workgroups with the large one.
+ *                   alone; longer ones by workgroups with the large one
+ *                   (default 20480).
  *   seg_mode    : 1 = one persistent launch: workgroups sum the long
  *                 segments of their term range, then their wavefronts claim
  *                 short segments from a device-wide cursor, longest length
  *                 class first; 0 = two launches (long segments, then short
  *                 ones on one workgroup per compute unit with an even split
- *                 of their total length).
+ *                 of their total weight: length plus a fixed cost per
+ *                 segment).
  *   seg_block   : threads per workgroup of the persistent launch: 256, 512
  *                 or 1024.
  *   seg_group   : segments per unit of the persistent launch's cursor, 1..64.
